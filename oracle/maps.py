@@ -1,0 +1,252 @@
+"""Block-space maps, written out plainly -- TEST INFRASTRUCTURE ONLY.
+
+Every map sends the linear index of a block of the parallel space Pi to a tile
+coordinate of the data space, or to "filtered" (-1).  Tiles are blocks of
+rho^m simplex elements; nb = ceil(n / rho) tiles per dimension.  Target tile
+sets:
+
+  T2 = {(x, y): 0 <= x <= y < nb}
+  T3 = {(x, y, z): 0 <= x <= y <= z < nb}
+
+Block linearisation (the layout of a tile dump): x varies fastest, then y,
+then z.  For the 3-simplex lambda map the linear index first runs over Pi3 and
+then over the lambda2 grid that covers the plane y = z.
+
+Integer arithmetic only (Python ints or int64 numpy), no floating point.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+FILTERED = -1
+
+
+def next_pow2(v: int) -> int:
+    p = 1
+    while p < v:
+        p *= 2
+    return p
+
+
+def floor_log2(v: np.ndarray) -> np.ndarray:
+    """floor(log2 v) for v >= 1, by counting the powers of two not above v."""
+    v = np.asarray(v, dtype=np.int64)
+    out = np.full(v.shape, -1, dtype=np.int64)
+    p = 1
+    while True:
+        ge = v >= p
+        if not ge.any():
+            break
+        out += ge
+        p *= 2
+    return out
+
+
+# --------------------------------------------------------------------------
+# lambda2 (paper Sec. III-A, the 2-simplex map).  The parallel space is the
+# orthotope (nb/2) x (nb+1).  Rows 1..nb-1 follow the paper's map: with
+# b = 2^floor(log2 w_y) (the recursion level of the row) and q = floor(w_x / b)
+# (which sub-orthotope of that level), lambda(w) = (w_x + q b, w_y + 2 q b),
+# which always lands strictly above the diagonal.  The paper leaves the
+# diagonal to the extra n blocks of S_{n+1} (V(S_n) + n = V(Delta_n)); here
+# row 0 carries tiles (w_x, w_x) and row nb carries (nb/2 + w_x, nb/2 + w_x).
+# A grid of nb = 1 is one block mapped to (0, 0).
+# Non-power-of-two nb: "approach from above" -- build the grid for
+# nb' = 2^ceil(log2 nb) and filter tiles with a coordinate >= nb.
+def pi2_extent(nb: int) -> tuple[int, int]:
+    nbp = next_pow2(nb)
+    if nbp == 1:
+        return (1, 1)
+    return (nbp // 2, nbp + 1)
+
+
+def lambda2_tiles(nb: int) -> np.ndarray:
+    nbp = next_pow2(nb)
+    ex, ey = pi2_extent(nb)
+    wy, wx = np.divmod(np.arange(ex * ey, dtype=np.int64), ex)
+    if nbp == 1:
+        t = np.zeros((1, 2), dtype=np.int64)
+    else:
+        t = np.empty((ex * ey, 2), dtype=np.int64)
+        top = wy == 0
+        bot = wy == nbp
+        mid = ~(top | bot)
+        t[top, 0] = wx[top]
+        t[top, 1] = wx[top]
+        t[bot, 0] = nbp // 2 + wx[bot]
+        t[bot, 1] = nbp // 2 + wx[bot]
+        b = 2 ** floor_log2(np.maximum(wy[mid], 1))
+        q = wx[mid] // b
+        t[mid, 0] = wx[mid] + q * b
+        t[mid, 1] = wy[mid] + 2 * q * b
+    bad = (t >= nb).any(axis=1)
+    t[bad] = FILTERED
+    return t
+
+
+# --------------------------------------------------------------------------
+# lambda3 (paper Sec. III-C, the alternative 3-simplex map with two recursion
+# branches).  The paper's closed form for the "diagonal or outside" case is
+# not recoverable from the text (its figures are lost and the printed offsets
+# do not round-trip), so this is the reading kept here; it has every property
+# the section states:
+#   * a main orthotope (nb/2) x (nb/2) x (nb/2 + nb/4) (the paper's
+#     (n/2) x (n/2) x 3(n-1)/4, read with integer extents);
+#   * its first nb/2 z-slices form the main (nb/2)^3 cube, moved as one piece;
+#   * the remaining z-slices reuse the 2-simplex parameters (b, q) of
+#     (w_x, w_y) with z shifted down by nb/2;
+#   * a two-case rule (inside / diagonal-or-outside) folds each b^3 cube of
+#     blocks across its diagonal plane onto the data space;
+#   * O(1) integer work and 12.5% extra volume (|Pi3| -> 9/8 |T3 minus plane|).
+# Target of Pi3: T3s = {x <= y < z}.  Each level b of the recursion owns the
+# cubes {o <= x < o+b <= z < o+2b}, o = 2 q b, of T3s; such a cube splits into
+# the prisms {x < o+b <= y < z} and {x <= y < o+b <= z} of b^2(b-1)/2 and
+# b^2(b+1)/2 tiles, together b^3.  A block (u, v, w) of a b^3 block-cube goes
+#   v <  w : (o + u,  o + b + v,  o + b + w)   (first prism)
+#   v >= w : (o + w,  o + v,      o + b + u)   (second prism)
+# The main cube is level b = nb/2 with o = 0 and (u, v, w) = (w_x, w_y, w_z).
+# A slab block has w = w_z - nb/2; it is filtered if w_y = 0 or w >= b, else
+# b = 2^floor(log2 w_y), q = floor(w_x / b), u = w_x - q b, v = w_y - b.
+# The plane y = z (tiles (x, y, y), x <= y) comes from a lambda2 grid over nb.
+def pi3_extent(nb: int) -> tuple[int, int, int]:
+    nbp = next_pow2(nb)
+    return (nbp // 2, nbp // 2, nbp // 2 + nbp // 4)
+
+
+def _fold(o, b, u, v, w):
+    first = v < w
+    x = np.where(first, o + u, o + w)
+    y = np.where(first, o + b + v, o + v)
+    z = np.where(first, o + b + w, o + b + u)
+    return x, y, z
+
+
+def lambda3_main_tiles(nb: int) -> np.ndarray:
+    nbp = next_pow2(nb)
+    ex, ey, ez = pi3_extent(nb)
+    tot = ex * ey * ez
+    idx = np.arange(tot, dtype=np.int64)
+    t = np.full((tot, 3), FILTERED, dtype=np.int64)
+    if tot == 0:
+        return t
+    wx = idx % ex
+    wy = (idx // ex) % ey
+    wz = idx // (ex * ey)
+    half = nbp // 2
+    cube = wz < half
+    # main cube: level b = nb/2, o = 0
+    x, y, z = _fold(0, half, wx[cube], wy[cube], wz[cube])
+    t[cube, 0], t[cube, 1], t[cube, 2] = x, y, z
+    # slab
+    s = ~cube
+    w = wz[s] - half
+    wys = wy[s]
+    wxs = wx[s]
+    valid = wys >= 1
+    b = np.where(valid, 2 ** floor_log2(np.maximum(wys, 1)), 1)
+    valid &= w < b
+    q = wxs // b
+    u = wxs - q * b
+    v = wys - b
+    o = 2 * q * b
+    x, y, z = _fold(o, b, u, v, w)
+    ts = np.stack([x, y, z], axis=1)
+    ts[~valid] = FILTERED
+    t[s] = ts
+    bad = (t >= nb).any(axis=1)
+    t[bad] = FILTERED
+    return t
+
+
+def lambda3_tiles(nb: int) -> np.ndarray:
+    main = lambda3_main_tiles(nb)
+    plane2 = lambda2_tiles(nb)
+    plane = np.full((plane2.shape[0], 3), FILTERED, dtype=np.int64)
+    ok = plane2[:, 0] >= 0
+    plane[ok, 0] = plane2[ok, 0]
+    plane[ok, 1] = plane2[ok, 1]
+    plane[ok, 2] = plane2[ok, 1]
+    return np.concatenate([main, plane], axis=0)
+
+
+# --------------------------------------------------------------------------
+# Bounding box (paper Sec. I): the identity over nb^m blocks, keeping only the
+# blocks inside the simplex.
+def bbox2_tiles(nb: int) -> np.ndarray:
+    y, x = np.divmod(np.arange(nb * nb, dtype=np.int64), nb)
+    t = np.stack([x, y], axis=1)
+    t[x > y] = FILTERED
+    return t
+
+
+def bbox3_tiles(nb: int) -> np.ndarray:
+    idx = np.arange(nb ** 3, dtype=np.int64)
+    x = idx % nb
+    y = (idx // nb) % nb
+    z = idx // (nb * nb)
+    t = np.stack([x, y, z], axis=1)
+    t[(x > y) | (y > z)] = FILTERED
+    return t
+
+
+# --------------------------------------------------------------------------
+# Linear enumeration g: Z^1 -> Z^m (paper Sec. I): block k is the k-th tile
+# when T2 is listed by y then x, and T3 by z, then y, then x.  Tri(y) =
+# y(y+1)/2 tiles have a smaller y; Tet(z) = z(z+1)(z+2)/6 have a smaller z.
+# The root of the quadratic / cubic is found here by exact search over the
+# integer tables, not by floating point.
+def linear2_tiles(nb: int) -> np.ndarray:
+    k = np.arange(nb * (nb + 1) // 2, dtype=np.int64)
+    yy = np.arange(nb + 1, dtype=np.int64)
+    tri = yy * (yy + 1) // 2
+    y = np.searchsorted(tri, k, side="right") - 1
+    x = k - tri[y]
+    return np.stack([x, y], axis=1)
+
+
+def linear3_tiles(nb: int) -> np.ndarray:
+    k = np.arange(nb * (nb + 1) * (nb + 2) // 6, dtype=np.int64)
+    zz = np.arange(nb + 1, dtype=np.int64)
+    tet = zz * (zz + 1) * (zz + 2) // 6
+    z = np.searchsorted(tet, k, side="right") - 1
+    r = k - tet[z]
+    tri = zz * (zz + 1) // 2
+    y = np.searchsorted(tri, r, side="right") - 1
+    x = r - tri[y]
+    return np.stack([x, y, z], axis=1)
+
+
+MAPS = {"lambda": 0, "bbox": 1, "linear": 2}
+
+
+def tiles(m: int, nb: int, kind: str) -> np.ndarray:
+    """Tile dump of map ``kind`` ('lambda', 'bbox', 'linear') for T2 (m=2) or T3 (m=3)."""
+    if m == 2:
+        return {"lambda": lambda2_tiles, "bbox": bbox2_tiles, "linear": linear2_tiles}[kind](nb)
+    if m == 3:
+        return {"lambda": lambda3_tiles, "bbox": bbox3_tiles, "linear": linear3_tiles}[kind](nb)
+    raise ValueError(m)
+
+
+def target_tiles(m: int, nb: int) -> set:
+    """The target tile set, by nested loops."""
+    if m == 2:
+        return {(x, y) for y in range(nb) for x in range(y + 1)}
+    return {(x, y, z) for z in range(nb) for y in range(z + 1) for x in range(y + 1)}
+
+
+def check_bijection(t: np.ndarray, m: int, nb: int) -> tuple[bool, str]:
+    """True iff the non-filtered rows of a dump are distinct and cover the target."""
+    valid = t[:, 0] >= 0
+    if (t[~valid] != FILTERED).any():
+        return False, "partially filtered row"
+    vt = t[valid]
+    if (vt < 0).any() or (vt >= nb).any():
+        return False, "tile out of range"
+    got = set(map(tuple, vt.tolist()))
+    if len(got) != vt.shape[0]:
+        return False, f"{vt.shape[0] - len(got)} duplicate tiles"
+    tgt = target_tiles(m, nb)
+    if got != tgt:
+        return False, f"missing {len(tgt - got)}, extra {len(got - tgt)}"
+    return True, "ok"

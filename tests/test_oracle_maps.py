@@ -1,0 +1,218 @@
+"""Pins for the oracle's block-space maps and the paper's volume formulas.
+
+Each check ties the oracle to something other than its own code: the
+hand-derived tables in tests/golden, brute-force set equality with the target
+simplices, the recursive orthotope sets of Sec. III (built here by recursion,
+without any log2 / clz), and the closed-form volumes of Sec. I and III.
+"""
+import os
+from fractions import Fraction
+from math import comb, factorial
+
+import numpy as np
+import pytest
+
+from oracle import maps
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _read_golden(name):
+    rows = []
+    with open(os.path.join(GOLDEN, name)) as f:
+        for line in f:
+            line = line.strip()
+            if line and not line.startswith("#"):
+                rows.append([int(v) for v in line.split()])
+    return np.array(rows, dtype=np.int64)
+
+
+def test_floor_log2_matches_bit_length():
+    v = np.arange(1, 5000)
+    assert (maps.floor_log2(v) == np.array([int(x).bit_length() - 1 for x in v])).all()
+
+
+def test_lambda2_golden_nb8():
+    g = _read_golden("lambda2_nb8.txt")
+    t = maps.lambda2_tiles(8)
+    ex, ey = maps.pi2_extent(8)
+    assert (ex, ey) == (4, 9)
+    for wx, wy, X, Y in g:
+        assert tuple(t[wy * ex + wx]) == (X, Y)
+    assert len(g) == t.shape[0]
+
+
+def test_lambda3_golden_nb4():
+    g = _read_golden("lambda3_nb4.txt")
+    t = maps.lambda3_main_tiles(4)
+    ex, ey, ez = maps.pi3_extent(4)
+    assert (ex, ey, ez) == (2, 2, 3)
+    for wx, wy, wz, X, Y, Z in g:
+        assert tuple(t[(wz * ey + wy) * ex + wx]) == (X, Y, Z)
+    assert len(g) == t.shape[0]
+
+
+@pytest.mark.parametrize("kind", ["lambda", "bbox", "linear"])
+@pytest.mark.parametrize("nb", [1, 2, 3, 4, 5, 7, 8, 12, 16, 33, 64, 100, 256])
+def test_map2_bijection(kind, nb):
+    ok, msg = maps.check_bijection(maps.tiles(2, nb, kind), 2, nb)
+    assert ok, msg
+
+
+@pytest.mark.parametrize("kind", ["lambda", "bbox", "linear"])
+@pytest.mark.parametrize("nb", [1, 2, 3, 4, 5, 6, 8, 12, 16, 32])
+def test_map3_bijection(kind, nb):
+    ok, msg = maps.check_bijection(maps.tiles(3, nb, kind), 3, nb)
+    assert ok, msg
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("nb", [512, 1024])
+def test_lambda2_bijection_large(nb):
+    ok, msg = maps.check_bijection(maps.lambda2_tiles(nb), 2, nb)
+    assert ok, msg
+
+
+@pytest.mark.parametrize("nb", [64, 128])
+def test_lambda3_bijection_large(nb):
+    ok, msg = maps.check_bijection(maps.lambda3_tiles(nb), 3, nb)
+    assert ok, msg
+
+
+def _recursive_s2(n, off=0):
+    """Tiles of the recursive set S2_n (Sec. III-A): one (n/2)^2 square over the
+    diagonal plus two copies of S2_{n/2}; returns {level size: set of tiles}."""
+    out = {}
+    if n < 2:
+        return out
+    h = n // 2
+    out.setdefault(h, set()).update((off + x, off + h + y) for x in range(h) for y in range(h))
+    for sub in (_recursive_s2(h, off), _recursive_s2(h, off + h)):
+        for b, s in sub.items():
+            out.setdefault(b, set()).update(s)
+    return out
+
+
+@pytest.mark.parametrize("nb", [2, 4, 8, 32, 128])
+def test_lambda2_rows_follow_recursive_set(nb):
+    """Rows [b, 2b) of Pi2 map exactly onto the level-b squares of S2, and
+    Pi2 has zero filtered blocks and exactly V(Delta2) blocks."""
+    t = maps.lambda2_tiles(nb)
+    ex, ey = maps.pi2_extent(nb)
+    assert ex * ey == nb * (nb + 1) // 2
+    assert (t[:, 0] >= 0).all()
+    levels = _recursive_s2(nb)
+    assert sum(len(s) for s in levels.values()) == nb * (nb - 1) // 2  # V(S2_n) = n(n-1)/2
+    for b, sq in levels.items():
+        rows = t[b * ex:(2 * b) * ex]
+        assert set(map(tuple, rows.tolist())) == sq
+        # within a square the map is a translation of the block grid
+        wy, wx = np.divmod(np.arange(b * ex, 2 * b * ex), ex)
+        o = rows[:, 0] - (wx % b)
+        assert ((rows[:, 1] - wy) == o).all()
+
+
+def _recursive_s3(n, off=0):
+    """Cross cubes of the two-branch recursive set S3_n (Sec. III-C): the
+    tiles {off <= x < off+h <= z < off+2h, x <= y < z} (h = n/2) plus two
+    copies of S3_{n/2}.  Returns {level h: set of tiles}."""
+    out = {}
+    if n < 2:
+        return out
+    h = n // 2
+    cube = {(x, y, z) for x in range(off, off + h) for z in range(off + h, off + n)
+            for y in range(x, z)}
+    out.setdefault(h, set()).update(cube)
+    for sub in (_recursive_s3(h, off), _recursive_s3(h, off + h)):
+        for b, s in sub.items():
+            out.setdefault(b, set()).update(s)
+    return out
+
+
+@pytest.mark.parametrize("nb", [2, 4, 8, 16, 32])
+def test_lambda3_levels_follow_two_branch_set(nb):
+    """The main cube covers the level-nb/2 cross cube; slab rows w_y in [b, 2b)
+    cover the level-b cubes; each cross cube holds b^3 tiles; the level sizes
+    follow V(S3_n) = (n/2)^3 + 2 V(S3_{n/2}) = (n^3 - n)/6."""
+    t = maps.lambda3_main_tiles(nb)
+    ex, ey, ez = maps.pi3_extent(nb)
+    levels = _recursive_s3(nb)
+    total = 0
+    for b, cubes in levels.items():
+        assert len(cubes) == (nb // (2 * b)) * b ** 3
+        total += len(cubes)
+    assert total == (nb ** 3 - nb) // 6
+    idx = np.arange(t.shape[0])
+    wx, wy, wz = idx % ex, (idx // ex) % ey, idx // (ex * ey)
+    half = nb // 2
+    main = set(map(tuple, t[wz < half].tolist()))
+    assert main == levels[half]
+    for b in [bb for bb in levels if bb < half]:
+        sel = (wz >= half) & (wy >= b) & (wy < 2 * b) & (t[:, 0] >= 0)
+        assert set(map(tuple, t[sel].tolist())) == levels[b]
+
+
+@pytest.mark.parametrize("nb", [4, 8, 16, 64, 128, 256])
+def test_lambda3_extra_volume(nb):
+    """|Pi3| = 3 nb^3 / 16 and |Pi3| / |T3 minus plane| -> 9/8 (12.5% extra, Sec. III-C)."""
+    ex, ey, ez = maps.pi3_extent(nb)
+    v = ex * ey * ez
+    assert v == 3 * nb ** 3 // 16
+    s = (nb ** 3 - nb) // 6
+    if nb <= 128:
+        t = maps.lambda3_main_tiles(nb)
+        assert int((t[:, 0] >= 0).sum()) == s
+    ratio = v / s
+    if nb >= 128:
+        assert abs(ratio - 9 / 8) < 2e-4
+    assert ratio >= 9 / 8
+
+
+# --------------------------------------------------------------------------
+# Volume formulas of Sec. I and III, against brute-force counting.
+@pytest.mark.parametrize("n", [1, 2, 3, 7, 16, 30])
+def test_simplex_volume_eq2(n):
+    cnt2 = sum(1 for x in range(n) for y in range(n) if x + y <= n - 1)
+    cnt3 = sum(1 for x in range(n) for y in range(n) for z in range(n) if x + y + z <= n - 1)
+    assert cnt2 == comb(n + 1, 2) == n * (n + 1) // 2
+    assert cnt3 == comb(n + 2, 3) == n * (n + 1) * (n + 2) // 6
+    # pairs / triplets form used by the build: the same counts
+    assert cnt2 == sum(1 for i in range(n) for j in range(i, n))
+    assert cnt3 == sum(1 for i in range(n) for j in range(i, n) for k in range(j, n))
+    # stacking identity, eq. (3)
+    assert comb(n + 2, 3) == sum(comb(i + 1, 2) for i in range(1, n + 1))
+
+
+def test_bbox_waste_limit():
+    """V(Pi)/V(Delta) - 1 -> m! - 1 for the bounding box (Sec. I)."""
+    for m in (2, 3, 4):
+        n = 4096
+        r = Fraction(n ** m, comb(n + m - 1, m)) - 1
+        assert abs(float(r) - (factorial(m) - 1)) < m * m * factorial(m) / n
+
+
+def _vol_rec(n, m, beta):
+    if n < 2:
+        return 0
+    return (n // 2) ** m + beta * _vol_rec(n // 2, m, beta)
+
+
+@pytest.mark.parametrize("k", range(1, 12))
+def test_recursive_set_volumes(k):
+    n = 2 ** k
+    assert _vol_rec(n, 2, 2) == n * (n - 1) // 2                      # Sec. III-A
+    assert _vol_rec(n, 3, 2) == (n ** 3 - n) // 6                     # Sec. III-C
+    assert 5 * _vol_rec(n, 3, 3) == n ** 3 - 3 ** k                   # Sec. III-B (with the /5)
+    for m in (2, 3, 4, 5, 6, 7):                                      # Sec. III-D, r = 1/2, beta = 2
+        assert _vol_rec(n, m, 2) * (2 ** m - 2) == n ** m - n
+
+
+def test_recursive_set_limits():
+    n = 2 ** 40
+    # three-branch set: 20% extra over the tetrahedron
+    assert abs(Fraction(n ** 3 - 3 ** 40, 5) / comb(n + 2, 3) - 1 - Fraction(1, 5)) < 1e-9
+    for m, lim in ((4, Fraction(5, 7)), (5, 3), (7, 39)):
+        v = Fraction(n ** m - n, 2 ** m - 2)
+        a = v / comb(n - 1 + m - 1, m) - 1
+        assert abs(float(a - lim)) < 1e-6
+        assert Fraction(factorial(m), 2 ** m - 2) - 1 == lim
