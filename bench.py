@@ -1,0 +1,290 @@
+"""Benchmark of the whole hot path on one MI355X.
+
+One step = one pass over every hot-path step at full size:
+  * packed EDM, n = 65,536, d = 64, FP32 difference form, lambda2 map;
+  * packed EDM via the Gram form, n = 32,768, d = 512, split BF16 on MFMA,
+    lambda2 map;
+  * Axilrod-Teller + Lennard-Jones energy and gradient (forward + backward),
+    n = 8,192 RSA particles, lambda3 map (triplets) and lambda2 map (pairs).
+The metric is simplex elements per second over the step (pairs of both EDMs,
+triplets, LJ pairs).  Inputs are synthetic (seeded), resident in HBM before the
+timed region.  Kernel durations come from HIP events the library records on
+the launch stream; bounding-box and linear-map runs of the same steps are timed
+after the main loop for the lambda-vs-bounding-box comparison.  The oracle is
+timed on a bounded sample on the host cores (cpu_baseline).
+
+    python bench.py [--steps K] [--warmup W] [--no-cpu-baseline] [--no-compare]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# published MI355X peaks
+PEAK_HBM = 8.0e12          # B/s
+PEAK_FP32 = 157.3e12       # FLOP/s, vector FP32 (packed); 78.6e12 without packed FP32
+PEAK_BF16 = 2.5e15         # FLOP/s, dense MFMA
+AT_FLOPS_FWD, AT_FLOPS_FWD_BWD = 20, 80   # declared flops per triplet
+LJ_FLOPS = 30                              # declared flops per pair (fwd + bwd)
+
+N_EDM, D_EDM = 65536, 64
+N_GRAM, D_GRAM = 32768, 512
+N_AT = 8192
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=5)
+    p.add_argument("--warmup", type=int, default=2)
+    p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--no-compare", action="store_true")
+    p.add_argument("--only", default="", help="comma list of edm,gram,at (default all)")
+    return p.parse_args()
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(each step is one GPU's share at its real shape)", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import paper_1610_07394_amd as smx
+    import synth
+
+    only = set(args.only.split(",")) if args.only else {"edm", "gram", "at"}
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    log("generating inputs")
+    X2 = torch.from_numpy(synth.workload_input("edm_n65536_d64")).to(dev)
+    X3 = torch.from_numpy(synth.workload_input("gram_n32768_d512")).to(dev)
+    X5 = torch.from_numpy(synth.workload_input("at_lj_n8192")).to(dev)
+    D2 = torch.empty(N_EDM * (N_EDM + 1) // 2, dtype=torch.float32, device=dev) if "edm" in only else None
+    D3 = torch.empty(N_GRAM * (N_GRAM + 1) // 2, dtype=torch.float32, device=dev) if "gram" in only else None
+    ws3 = torch.empty(smx.workspace_bytes(1, N_GRAM, D_GRAM, 2), dtype=torch.uint8, device=dev)
+    ws5 = torch.empty(smx.workspace_bytes(2, N_AT), dtype=torch.uint8, device=dev)
+    pot = smx.Pot(nu=1.0, at=True, lj=True, eps=1.0, sigma=1.0, rc=3.0)
+    gradE = torch.ones(1, dtype=torch.float64, device=dev)
+    dX = torch.empty((N_AT, 3), dtype=torch.float32, device=dev)
+
+    def step(kind="lambda", parts=only):
+        if "edm" in parts:
+            smx.edm_packed(X2, kind, "fp32", out=D2)
+        if "gram" in parts:
+            smx.edm_packed(X3, kind, "split_bf16", out=D3, ws=ws3)
+        if "at" in parts:
+            # forward + backward: energy and dE/dx in one pass, then the
+            # backward scaling by the incoming gradient
+            E, G = smx.triplet_energy_grad(X5, pot, kind, ws=ws5)
+            smx._check(smx.lib().smx_scale_grad(G.data_ptr(), N_AT, gradE.data_ptr(), dX.data_ptr(),
+                                                smx._stream()))
+
+    elements = {
+        "edm": N_EDM * (N_EDM + 1) // 2,
+        "gram": N_GRAM * (N_GRAM + 1) // 2,
+        "at": math.comb(N_AT, 3) + math.comb(N_AT, 2),
+    }
+    total_elems = sum(elements[p] for p in only)
+
+    log("warmup")
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    smx.profile_enable(True)
+    smx.profile_reset()
+    log(f"timing {args.steps} steps")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_step = (t1 - t0) * 1e3 / args.steps
+    kern = {k: smx.profile_read(k) for k in smx.KERNELS}
+    smx.profile_enable(False)
+    kavg = {k: (v[0] / v[1] if v[1] else 0.0) for k, v in kern.items()}
+    value = total_elems / (ms_step / 1e3)
+
+    # ---- per-component rooflines (algorithmic units per launch / avg launch time)
+    comps = {}
+    if "edm" in only:
+        t = kavg["edm_diff"] / 1e3
+        e = elements["edm"]
+        comps["edm_fp32_n65536_d64"] = {
+            "elements": e, "kernel_ms": kavg["edm_diff"], "elements_per_s": e / t,
+            "alu_tflops": 3 * D_EDM * e / t / 1e12, "alu_frac": 3 * D_EDM * e / t / PEAK_FP32,
+            "hbm_gbs": 4 * e / t / 1e9, "hbm_frac": 4 * e / t / PEAK_HBM}
+    if "gram" in only:
+        t = kavg["edm_gram"] / 1e3
+        e = elements["gram"]
+        comps["edm_split_bf16_n32768_d512"] = {
+            "elements": e, "kernel_ms": kavg["edm_gram"], "prep_ms": kavg["gram_prep"],
+            "elements_per_s": e / (t + kavg["gram_prep"] / 1e3),
+            "mfma_tflops": 3 * 2 * D_GRAM * e / t / 1e12, "mfma_frac": 3 * 2 * D_GRAM * e / t / PEAK_BF16,
+            "hbm_gbs": 4 * e / t / 1e9, "hbm_frac": 4 * e / t / PEAK_HBM}
+    if "at" in only:
+        t = kavg["triplet_grad"] / 1e3
+        tri = math.comb(N_AT, 3)
+        comps["at_lj_n8192_fwd_bwd"] = {
+            "triplets": tri, "pairs": math.comb(N_AT, 2), "kernel_ms": kavg["triplet_grad"],
+            "lj_ms": kavg["lj"], "triplets_per_s": tri / t,
+            "alu_tflops": AT_FLOPS_FWD_BWD * tri / t / 1e12, "alu_frac": AT_FLOPS_FWD_BWD * tri / t / PEAK_FP32}
+
+    # dominant kernel (largest time per step)
+    per_step = {k: kern[k][0] / args.steps for k in kern}
+    dom = max(per_step, key=per_step.get)
+    if dom == "triplet_grad":
+        t = kavg[dom] / 1e3
+        ach = AT_FLOPS_FWD_BWD * math.comb(N_AT, 3) / t
+        roof = {"kernel": "at_kernel<lambda, grad>", "bound": "alu", "achieved": ach / 1e12,
+                "peak": PEAK_FP32 / 1e12, "unit": "TFLOP/s", "frac": ach / PEAK_FP32, "traffic": None,
+                "per_unit": "80 flops per triplet (20 forward + 60 backward), 9.159e10 triplets per launch"}
+    elif dom == "edm_diff":
+        t = kavg[dom] / 1e3
+        ach = 3 * D_EDM * elements["edm"] / t
+        roof = {"kernel": "edm_diff_kernel<lambda>", "bound": "alu", "achieved": ach / 1e12,
+                "peak": PEAK_FP32 / 1e12, "unit": "TFLOP/s", "frac": ach / PEAK_FP32, "traffic": None,
+                "per_unit": "3 d flops per pair, 2.1475e9 pairs per launch"}
+    else:
+        t = kavg[dom] / 1e3
+        ach = 3 * 2 * D_GRAM * elements["gram"] / t
+        roof = {"kernel": "edm_gram_kernel<lambda, split>", "bound": "mfma", "achieved": ach / 1e12,
+                "peak": PEAK_BF16 / 1e12, "unit": "TFLOP/s", "frac": ach / PEAK_BF16, "traffic": None,
+                "per_unit": "6 d flops per pair (3 BF16 products), 5.369e8 pairs per launch"}
+
+    # ---- lambda vs bounding box vs linear (same steps, timed after the main loop)
+    compare = None
+    if not args.no_compare:
+        compare = {}
+        for kind in ("bbox", "linear"):
+            step(kind)  # warm
+            torch.cuda.synchronize()
+            smx.profile_enable(True)
+            smx.profile_reset()
+            for _ in range(args.steps):
+                step(kind)
+            kk = {k: smx.profile_read(k) for k in ("edm_diff", "edm_gram", "triplet_grad", "lj")}
+            smx.profile_enable(False)
+            compare[kind] = {k: (v[0] / v[1] if v[1] else None) for k, v in kk.items()}
+        compare["lambda"] = {k: kavg[k] for k in ("edm_diff", "edm_gram", "triplet_grad", "lj")}
+        sp = {}
+        for k in ("edm_diff", "edm_gram", "triplet_grad"):
+            if compare["bbox"].get(k) and compare["lambda"].get(k):
+                sp[k] = compare["bbox"][k] / compare["lambda"][k]
+        compare["speedup_lambda_vs_bbox"] = sp
+        # map-only parallel spaces (paper-like granularity: rho = 16 pairs, rho = 8 triplets)
+        mo = {}
+        for kind in ("lambda", "bbox", "linear"):
+            for m, n, rho in ((2, N_EDM, 16), (3, N_AT, 8)):
+                fn = smx.simplex_map2 if m == 2 else smx.simplex_map3
+                fn(n, rho, kind, strict=(m == 3), tiles=False)
+                torch.cuda.synchronize()
+                smx.profile_enable(True)
+                smx.profile_reset()
+                for _ in range(3):
+                    fn(n, rho, kind, strict=(m == 3), tiles=False)
+                ms, c = smx.profile_read("map2" if m == 2 else "map3")
+                smx.profile_enable(False)
+                mo[f"map{m}_{kind}_n{n}_rho{rho}_ms"] = ms / c
+        compare["map_only"] = mo
+
+    # ---- CPU baseline: the FP64 oracle on a bounded sample, host cores
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(only, elements, total_elems)
+
+    out = {
+        "metric": "simplex elements/sec (lambda map) for packed EDM + AT/LJ fwd+bwd",
+        "value": value,
+        "unit": "elements/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic (seeded: N(0,1) EDM inputs, RSA particles in a cube of side 20, dmin 0.8)",
+        "config": {
+            "workload": "step = edm_fp32 n=65536 d=64 + edm_gram split-bf16 n=32768 d=512 + "
+                        "axilrod-teller + lennard-jones fwd+bwd n=8192 (lambda maps)",
+            "elements_per_step": total_elems,
+            "parts": sorted(only),
+        },
+        "roofline": roof,
+        "components": comps,
+        "kernel_ms_avg": kavg,
+        "compare": compare,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out))
+
+
+def cpu_baseline(only, elements, total_elems):
+    import numpy as np
+
+    import oracle
+    import synth
+
+    cores = oracle.threads()
+    secs_per_step = 0.0
+    samples = []
+    if "edm" in only:
+        X = synth.workload_input("edm_n65536_d64")
+        r = 256
+        t0 = time.perf_counter()
+        oracle.edm_rows(X, 0, r)
+        dt = time.perf_counter() - t0
+        e = oracle.packed_offset(r, N_EDM)
+        secs_per_step += elements["edm"] * dt / e
+        samples.append(f"EDM d=64 rows 0..{r} ({e} pairs, {dt:.2f}s)")
+    if "gram" in only:
+        X = synth.workload_input("gram_n32768_d512")
+        r = 64
+        t0 = time.perf_counter()
+        oracle.edm_rows(X, 0, r)
+        dt = time.perf_counter() - t0
+        e = oracle.packed_offset(r, N_GRAM)
+        secs_per_step += elements["gram"] * dt / e
+        samples.append(f"EDM d=512 rows 0..{r} ({e} pairs, {dt:.2f}s)")
+    if "at" in only:
+        X = synth.workload_input("at_lj_n8192")
+        i1 = 24
+        t0 = time.perf_counter()
+        oracle.at_energy(X, 1.0, 0, i1)
+        dt_e = time.perf_counter() - t0
+        tri_e = sum(math.comb(N_AT - 1 - i, 2) for i in range(i1))
+        rows = [0, 1, 2, 3]
+        t0 = time.perf_counter()
+        oracle.at_grad_rows(X, rows, 1.0)
+        dt_g = time.perf_counter() - t0
+        tri_g = len(rows) * math.comb(N_AT - 1, 2)
+        t0 = time.perf_counter()
+        oracle.lj_energy(X)
+        oracle.lj_grad(X)
+        dt_lj = time.perf_counter() - t0
+        tri = math.comb(N_AT, 3)
+        secs_per_step += tri * dt_e / tri_e + tri * dt_g / tri_g + dt_lj
+        samples.append(f"AT energy i<{i1} ({tri_e} triplets, {dt_e:.2f}s); AT gradient of {len(rows)} particles "
+                       f"({tri_g} triplets, {dt_g:.2f}s); LJ energy+gradient full ({dt_lj:.2f}s)")
+    return {"value": total_elems / secs_per_step, "unit": "elements/s", "cores": cores, "kind": "oracle",
+            "sample": "; ".join(samples) + " -- scaled to one full step"}
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,196 @@
+/*
+ * smx.h -- C ABI of libsmx, recursive block-space maps onto discrete
+ * orthogonal simplices and the data-parallel work they drive, for AMD
+ * Instinct MI355X (gfx950).
+ *
+ * Paper: C. A. Navarro, B. Bustos, N. Hitschfeld, "Possibilities of Recursive
+ * GPU Mapping for Discrete Orthogonal Simplices" (arXiv:1610.07394).
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * - Pointers named d_* are device pointers (HIP device memory of the current
+ *   device); everything else is host memory.  The caller owns and allocates
+ *   every buffer, outputs and workspaces included: the library never
+ *   allocates, frees or synchronises.  Work is enqueued on `stream` (a
+ *   hipStream_t; NULL = the default stream) and is asynchronous.
+ * - Return value: an smx_status.  Arguments are validated on the host before
+ *   any HIP call; on failure nothing is enqueued and smx_last_error() holds a
+ *   message (per host thread).  SMX_EHIP reports a failed launch; faults inside
+ *   a kernel surface at the caller's next synchronisation.
+ * - Simplex elements.  Pairs: 0 <= i <= j < n ("le") or i < j ("lt").
+ *   Triplets: i <= j <= k < n ("le") or i < j < k ("lt").  The paper's
+ *   eq. (1) bounds the coordinate sum by n, but its volume, eq. (2), counts
+ *   the sum <= n-1 form; this library uses the equivalent pairs / triplets form,
+ *   with V = n(n+1)/2 and n(n+1)(n+2)/6 elements (Sec. I, eq. (2)).
+ * - Tiles.  Work is mapped per block: a block owns a tile of rho^m elements,
+ *   tile (X, Y[, Z]) holding elements (X rho + a, Y rho + b[, Z rho + c]).
+ *   nb = ceil(n / rho) tiles per dimension.  Tile targets are
+ *   T2 = {X <= Y < nb} and T3 = {X <= Y <= Z < nb}.
+ * - Maps (smx_map), i.e. how a launched block finds its tile:
+ *     SMX_MAP_LAMBDA  the O(1) recursive block-space map lambda (Sec. III-A for
+ *                     m = 2, Sec. III-C for m = 3).  Non-power-of-two nb uses
+ *                     the paper's "approach n from above" (Sec. III-A): the
+ *                     grid for the next power of two, blocks past nb filtered.
+ *     SMX_MAP_BBOX    bounding box: identity over an nb^m grid, blocks outside
+ *                     the simplex exit (Sec. I).
+ *     SMX_MAP_LINEAR  linear enumeration g: Z^1 -> Z^m (Sec. I): FP32 square /
+ *                     cube root of the block index plus an exact integer fix-up.
+ *   The map changes only the schedule.  EDM outputs are bit-identical across
+ *   maps; energies and gradients agree to rounding (atomic order).
+ * - Statistics (d_stats, nullable): int64[4] =
+ *     [0] elements visited, [1] checksum (wrapping uint64 sum of SplitMix64 of
+ *     each element's id), [2] blocks that mapped to a tile, [3] blocks launched.
+ *   Element ids: pairs le: i*n - i(i-1)/2 + (j-i) (the packed index);
+ *   pairs lt: j(j-1)/2 + i; triplets le: k(k+1)(k+2)/6 + j(j+1)/2 + i;
+ *   triplets lt: k(k-1)(k-2)/6 + j(j-1)/2 + i.  Each is a bijection onto
+ *   [0, V).  Requesting statistics selects a slower counting kernel.
+ */
+#ifndef SMX_H
+#define SMX_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    SMX_OK = 0,
+    SMX_EINVAL = 1,      /* bad argument (null pointer, negative size, bad enum, ...) */
+    SMX_EOVERFLOW = 2,   /* a size does not fit the index types */
+    SMX_EUNSUPPORTED = 3,/* valid request this build does not implement */
+    SMX_EHIP = 4         /* a HIP call or kernel launch failed */
+} smx_status;
+
+typedef enum { SMX_MAP_LAMBDA = 0, SMX_MAP_BBOX = 1, SMX_MAP_LINEAR = 2 } smx_map;
+
+typedef enum {
+    SMX_EDM_FP32_DIFF = 0,      /* sum_k (x_ik - x_jk)^2 in FP32 on the vector ALUs */
+    SMX_EDM_BF16_GRAM = 1,      /* |x_i|^2 + |x_j|^2 - 2 G_ij, G on BF16 MFMA, FP32 accumulation */
+    SMX_EDM_SPLITBF16_GRAM = 2  /* as 1 with G = hi.hi + hi.lo + lo.hi (split BF16) */
+} smx_edm_prec;
+
+/* Interaction potential for the triplet calls. */
+typedef struct {
+    double nu;        /* Axilrod-Teller coefficient */
+    int32_t at_on;    /* 1: include the Axilrod-Teller triplet energy */
+    int32_t lj_on;    /* 1: include Lennard-Jones pairs */
+    double lj_eps, lj_sigma, lj_rc; /* LJ epsilon, sigma, cutoff radius (> 0) */
+} smx_pot;
+
+/* Library version string. */
+const char *smx_version(void);
+
+/* Message of the last failed call on this host thread ("" if none). */
+const char *smx_last_error(void);
+
+/* Number of simplex elements: C(n+m-1, m) (paper eq. (2)) or C(n, m) when
+ * strict != 0, for m in {2, 3}.  Host only.  -1 on bad arguments or overflow. */
+int64_t smx_volume(int m, int64_t n, int strict);
+
+/* Number of blocks the map launches for n elements per dimension and tile
+ * edge rho (the |Pi| of the paper, in blocks), m in {2, 3}.  For
+ * SMX_MAP_LAMBDA and m = 3 this is |Pi3| plus the lambda2 grid of the plane
+ * Y = Z.  It sizes the tile dump of smx_simplex_map2/3.  Host only; -1 on bad
+ * arguments or overflow. */
+int64_t smx_parallel_blocks(int m, int64_t n, int rho, int map);
+
+/* The tiles of launched blocks first .. first+count-1, written to host memory
+ * tiles[count][m] in block order (-1 for a filtered block); the range must lie
+ * in [0, smx_parallel_blocks(m, n, rho, map)).  Evaluated on the host by the
+ * same inline map code the kernels use, for inspection and testing; no device
+ * work.  Host only. */
+int smx_map_tiles_host(int m, int64_t n, int rho, int map, int64_t first, int64_t count,
+                       int32_t *tiles);
+
+/* Workspace bytes the calls below need (0 if none).  `op`: 0 = simplex_map
+ * (any m), 1 = edm_packed, 2 = triplet calls.  Host only; 0 also on bad
+ * arguments. */
+size_t smx_workspace_bytes(int op, int64_t n, int64_t d, int prec, int map);
+
+/* Map dump over the 2-simplex (Sec. III-A).  Launches the parallel space of
+ * `map` for n elements per dimension and tile edge rho (a power of two in
+ * [1, 1024]); each block evaluates its map once and then visits the elements
+ * of its tile (pairs le, or lt when strict != 0), counting them into d_stats.
+ *   d_tiles  int32[smx_parallel_blocks(2, n, rho, map)][2] or NULL: tile (X, Y)
+ *            of each launched block, in block order (x fastest), or (-1, -1)
+ *            if the block is filtered.  Block order for LAMBDA: the
+ *            (nb'/2) x (nb'+1) grid, nb' = next power of two >= nb; BBOX: nb x nb;
+ *            LINEAR: one block per tile of T2.
+ *   d_stats  int64[4] or NULL (see above).
+ *   d_ws     smx_workspace_bytes(0, ...) bytes (required when d_stats != NULL).
+ * n = 0 enqueues nothing and leaves the outputs untouched. */
+int smx_simplex_map2(int64_t n, int rho, int map, int strict, int32_t *d_tiles,
+                     int64_t *d_stats, void *d_ws, size_t ws_bytes, void *stream);
+
+/* Map dump over the 3-simplex (Sec. III-C), as smx_simplex_map2 with
+ * triplets; rho a power of two in [1, 64].  d_tiles is
+ * int32[smx_parallel_blocks(3, n, rho, map)][3].  LAMBDA block order: the
+ * (nb'/2) x (nb'/2) x (nb'/2 + nb'/4) orthotope Pi3 (x fastest), then the
+ * lambda2 grid over nb whose tile (X, Y) is mapped to (X, Y, Y). */
+int smx_simplex_map3(int64_t n, int rho, int map, int strict, int32_t *d_tiles,
+                     int64_t *d_stats, void *d_ws, size_t ws_bytes, void *stream);
+
+/* Packed Euclidean distance matrix (paper Sec. I and II: the EDM is a
+ * 2-simplex problem whose upper triangle suffices).
+ *   d_X   FP32 [n][ldx] row-major, ldx >= d; read only.
+ *   d_D   FP32 [n(n+1)/2]: D[p(i,j)] = |x_i - x_j|^2 for i <= j,
+ *         p(i,j) = i n - i(i-1)/2 + (j - i) (row-major upper triangle with the
+ *         diagonal).  Diagonal entries are exactly 0.
+ *   prec  smx_edm_prec.  Gram variants round X to BF16 with round-to-nearest-even
+ *         (hi = bf16(x), lo = bf16(x - hi)), accumulate in FP32, add FP32 norms
+ *         |x|^2, clamp the result at 0.
+ *   d_ws  smx_workspace_bytes(1, n, d, prec, map) bytes (BF16 copies and norms
+ *         for the Gram variants, statistics slots), or NULL when that is 0.
+ *   d_stats nullable; counts pairs le. */
+int smx_edm_packed(const float *d_X, int64_t n, int64_t d, int64_t ldx, int map, int prec,
+                   float *d_D, void *d_ws, size_t ws_bytes, int64_t *d_stats, void *stream);
+
+/* Triplet + pair interaction energy on the 3-simplex (Sec. I: the
+ * triple-interaction n-body problem) and the 2-simplex (pair n-body).
+ *   E = nu sum_{i<j<k} (1 + 3 cos g_i cos g_j cos g_k) / (r_ij r_jk r_ik)^3     (at_on)
+ *     + sum_{i<j, r_ij < rc} 4 eps ((sigma/r)^12 - (sigma/r)^6)                 (lj_on)
+ * with open boundaries and an unshifted LJ cutoff; whether a pair is inside
+ * the cutoff is decided on s = fl(fma(dz,dz, fma(dy,dy, dx*dx))), d* = fl(x_j* - x_i*),
+ * against fl(rc*rc).  Coincident particles give inf/NaN (not checked).
+ *   d_X   FP32 [n][ldx], ldx >= 3 (only x, y, z are read).
+ *   d_E   FP64 [3]: total, Axilrod-Teller part, Lennard-Jones part.
+ *   d_ws  smx_workspace_bytes(2, n, 3, 0, map) bytes.
+ *   d_stats nullable, int64[8]: [0..3] triplets lt, [4..7] pairs lt.
+ * E = 0 for n < 3 (AT) and n < 2 (LJ). */
+int smx_triplet_energy(const float *d_X, int64_t n, int64_t ldx, const smx_pot *pot, int map,
+                       double *d_E, void *d_ws, size_t ws_bytes, int64_t *d_stats, void *stream);
+
+/* Energy and its gradient in one pass: d_E as above (nullable) and
+ * d_G FP32 [n][3] = dE/dx (forces are -d_G).  Per-pair derivatives are reduced
+ * per block and accumulated into an FP64 gradient in the workspace. */
+int smx_triplet_energy_grad(const float *d_X, int64_t n, int64_t ldx, const smx_pot *pot,
+                            int map, double *d_E, float *d_G, void *d_ws, size_t ws_bytes,
+                            void *stream);
+
+/* Backward of smx_triplet_energy: d_dX FP32 [n][3] = gradE[0] * dE/dx, where
+ * d_gradE is an FP64 device scalar (the incoming gradient of E). */
+int smx_triplet_energy_backward(const float *d_X, int64_t n, int64_t ldx, const smx_pot *pot,
+                                int map, const double *d_gradE, float *d_dX, void *d_ws,
+                                size_t ws_bytes, void *stream);
+
+/* d_out[q] = gradE[0] * d_G[q] for q < 3n (FP32 out, FP64 scale): the backward
+ * pass of smx_triplet_energy_grad's output, given the incoming gradient
+ * d_gradE (FP64 device scalar).  d_out may alias d_G. */
+int smx_scale_grad(const float *d_G, int64_t n, const double *d_gradE, float *d_out, void *stream);
+
+/* Kernel timing: when enabled, every main kernel launch is bracketed by HIP
+ * events on its own stream.  smx_profile_read synchronises on those events and
+ * returns the summed duration (ms) and launch count of kernel `kernel_id`
+ * (0 map2, 1 map3, 2 edm diff, 3 edm gram, 4 gram prep, 5 triplet energy,
+ * 6 triplet grad, 7 lj, 8 finalize) since the last reset; it returns SMX_EINVAL
+ * for an unknown id.  smx_profile_reset clears the totals.  Host only. */
+int smx_profile_enable(int on);
+int smx_profile_reset(void);
+int smx_profile_read(int kernel_id, double *total_ms, int64_t *launches);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SMX_H */

@@ -1,0 +1,290 @@
+"""Python binding of libsmx (recursive block-space maps onto discrete
+orthogonal simplices, MI355X / gfx950).
+
+Argument marshalling only: every step runs in the HIP kernels of libsmx.so,
+called through its C ABI (include/smx.h) with ctypes.  PyTorch provides device
+memory and the current HIP stream.  If libsmx.so is missing, or a tensor is not
+on the GPU, the calls raise; there is no CPU path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import torch
+
+__all__ = [
+    "MAPS", "PRECS", "SmxError", "Pot", "lib", "volume", "parallel_blocks", "map_tiles_host",
+    "workspace_bytes", "simplex_map2", "simplex_map3", "edm_packed", "triplet_energy",
+    "triplet_energy_grad", "triplet_energy_backward", "TripletEnergy", "profile_enable",
+    "profile_reset", "profile_read", "KERNELS",
+]
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsmx.so")
+
+MAPS = {"lambda": 0, "bbox": 1, "linear": 2}
+PRECS = {"fp32": 0, "bf16": 1, "split_bf16": 2}
+KERNELS = {"map2": 0, "map3": 1, "edm_diff": 2, "edm_gram": 3, "gram_prep": 4,
+           "triplet_energy": 5, "triplet_grad": 6, "lj": 7, "finalize": 8}
+
+_i32, _i64, _sz, _vp, _dbl = ctypes.c_int, ctypes.c_int64, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_double
+
+
+class _Pot(ctypes.Structure):
+    _fields_ = [("nu", ctypes.c_double), ("at_on", ctypes.c_int32), ("lj_on", ctypes.c_int32),
+                ("lj_eps", ctypes.c_double), ("lj_sigma", ctypes.c_double), ("lj_rc", ctypes.c_double)]
+
+
+@dataclass(frozen=True)
+class Pot:
+    """Axilrod-Teller coefficient nu and optional Lennard-Jones pairs."""
+    nu: float = 1.0
+    at: bool = True
+    lj: bool = False
+    eps: float = 1.0
+    sigma: float = 1.0
+    rc: float = 3.0
+
+    def _c(self) -> _Pot:
+        return _Pot(self.nu, int(self.at), int(self.lj), self.eps, self.sigma, self.rc)
+
+
+class SmxError(RuntimeError):
+    pass
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is not built; run paper_1610_07394_amd/build.py "
+                              "(or __graft_entry__.build())")
+        L = ctypes.CDLL(LIB_PATH)
+        L.smx_version.restype = ctypes.c_char_p
+        L.smx_last_error.restype = ctypes.c_char_p
+        L.smx_volume.argtypes = [_i32, _i64, _i32]
+        L.smx_volume.restype = _i64
+        L.smx_parallel_blocks.argtypes = [_i32, _i64, _i32, _i32]
+        L.smx_parallel_blocks.restype = _i64
+        L.smx_map_tiles_host.argtypes = [_i32, _i64, _i32, _i32, _i64, _i64, _vp]
+        L.smx_workspace_bytes.argtypes = [_i32, _i64, _i64, _i32, _i32]
+        L.smx_workspace_bytes.restype = _sz
+        for name in ("smx_simplex_map2", "smx_simplex_map3"):
+            getattr(L, name).argtypes = [_i64, _i32, _i32, _i32, _vp, _vp, _vp, _sz, _vp]
+        L.smx_edm_packed.argtypes = [_vp, _i64, _i64, _i64, _i32, _i32, _vp, _vp, _sz, _vp, _vp]
+        L.smx_triplet_energy.argtypes = [_vp, _i64, _i64, ctypes.POINTER(_Pot), _i32, _vp, _vp, _sz, _vp, _vp]
+        L.smx_triplet_energy_grad.argtypes = [_vp, _i64, _i64, ctypes.POINTER(_Pot), _i32, _vp, _vp, _vp,
+                                              _sz, _vp]
+        L.smx_triplet_energy_backward.argtypes = [_vp, _i64, _i64, ctypes.POINTER(_Pot), _i32, _vp, _vp,
+                                                  _vp, _sz, _vp]
+        L.smx_scale_grad.argtypes = [_vp, _i64, _vp, _vp, _vp]
+        L.smx_profile_enable.argtypes = [_i32]
+        L.smx_profile_read.argtypes = [_i32, ctypes.POINTER(_dbl), ctypes.POINTER(_i64)]
+        _lib = L
+    return _lib
+
+
+def version() -> str:
+    return lib().smx_version().decode()
+
+
+def _check(rc: int) -> None:
+    if rc == 0:
+        return
+    msg = lib().smx_last_error().decode()
+    if rc == 1:
+        raise ValueError(msg)
+    if rc == 2:
+        raise OverflowError(msg)
+    if rc == 3:
+        raise NotImplementedError(msg)
+    raise SmxError(msg)
+
+
+def _map(m) -> int:
+    return MAPS[m] if isinstance(m, str) else int(m)
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dev(t: torch.Tensor, name: str) -> int:
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a GPU tensor (got device {t.device})")
+    return t.data_ptr()
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+# ---------------------------------------------------------------- host queries
+def volume(m: int, n: int, strict: bool = False) -> int:
+    return int(lib().smx_volume(m, n, int(strict)))
+
+
+def parallel_blocks(m: int, n: int, rho: int, map="lambda") -> int:
+    v = int(lib().smx_parallel_blocks(m, n, rho, _map(map)))
+    if v < 0:
+        raise ValueError(f"no parallel space for m={m}, n={n}, rho={rho}, map={map}")
+    return v
+
+
+def map_tiles_host(m: int, n: int, rho: int, map="lambda", first: int = 0, count: int | None = None):
+    """Tiles of launched blocks [first, first + count), evaluated on the host (numpy int32 [count, m])."""
+    import numpy as np
+    if count is None:
+        count = parallel_blocks(m, n, rho, map) - first
+    out = np.empty((count, m), dtype=np.int32)
+    _check(lib().smx_map_tiles_host(m, n, rho, _map(map), first, count, out.ctypes.data))
+    return out
+
+
+def workspace_bytes(op: int, n: int, d: int = 3, prec: int = 0, map="lambda") -> int:
+    return int(lib().smx_workspace_bytes(op, n, d, prec, _map(map)))
+
+
+def _ws(nbytes: int, device) -> torch.Tensor | None:
+    if nbytes == 0:
+        return None
+    return torch.empty(nbytes, dtype=torch.uint8, device=device)
+
+
+# ---------------------------------------------------------------- map dumps
+def _simplex_map(m: int, n: int, rho: int, map, strict: bool, tiles: bool, stats: bool, device):
+    device = torch.device(device)
+    g = parallel_blocks(m, n, rho, map)
+    t = torch.empty((g, m), dtype=torch.int32, device=device) if tiles else None
+    s = torch.zeros(4, dtype=torch.int64, device=device) if stats else None
+    ws = _ws(workspace_bytes(0, n), device) if stats else None
+    fn = lib().smx_simplex_map2 if m == 2 else lib().smx_simplex_map3
+    _check(fn(n, rho, _map(map), int(strict), _ptr(t), _ptr(s), _ptr(ws), 0 if ws is None else ws.numel(),
+              _stream()))
+    return t, s
+
+
+def simplex_map2(n: int, rho: int, map="lambda", strict=False, tiles=True, stats=True, device="cuda"):
+    """Run the 2-simplex parallel space; returns (tiles int32 [G, 2] | None, stats int64 [4] | None)."""
+    return _simplex_map(2, n, rho, map, strict, tiles, stats, device)
+
+
+def simplex_map3(n: int, rho: int, map="lambda", strict=False, tiles=True, stats=True, device="cuda"):
+    """Run the 3-simplex parallel space; returns (tiles int32 [G, 3] | None, stats int64 [4] | None)."""
+    return _simplex_map(3, n, rho, map, strict, tiles, stats, device)
+
+
+# ---------------------------------------------------------------- EDM
+def edm_packed(X: torch.Tensor, map="lambda", prec="fp32", stats=False, out=None, ws=None):
+    """Packed upper-triangle squared distances of the rows of X (FP32 [n, d])."""
+    if X.dtype != torch.float32 or X.dim() != 2 or X.stride(1) != 1:
+        raise ValueError("X must be a row-major FP32 matrix")
+    n, d = X.shape
+    ldx = X.stride(0) if n > 0 else d
+    p = PRECS[prec] if isinstance(prec, str) else int(prec)
+    D = out if out is not None else torch.empty(n * (n + 1) // 2, dtype=torch.float32, device=X.device)
+    s = torch.zeros(4, dtype=torch.int64, device=X.device) if stats else None
+    need = workspace_bytes(1, n, d, p, map)
+    if ws is None and (p != 0 or stats):
+        ws = _ws(need, X.device)
+    _check(lib().smx_edm_packed(_dev(X, "X"), n, d, ldx, _map(map), p, _ptr(D), _ptr(ws),
+                                0 if ws is None else ws.numel(), _ptr(s), _stream()))
+    return (D, s) if stats else D
+
+
+# ---------------------------------------------------------------- triplets
+def _xarg(X: torch.Tensor):
+    if X.dtype != torch.float32 or X.dim() != 2 or X.shape[1] < 3 or X.stride(1) != 1:
+        raise ValueError("X must be a row-major FP32 [n, >=3] matrix")
+    return _dev(X, "X"), X.shape[0], (X.stride(0) if X.shape[0] > 0 else 3)
+
+
+def triplet_energy(X: torch.Tensor, pot: Pot = Pot(), map="lambda", stats=False, ws=None):
+    """Energy (FP64 [3]: total, AT, LJ); with stats=True also int64 [8] counters."""
+    xp, n, ldx = _xarg(X)
+    E = torch.empty(3, dtype=torch.float64, device=X.device)
+    s = torch.zeros(8, dtype=torch.int64, device=X.device) if stats else None
+    ws = ws if ws is not None else _ws(workspace_bytes(2, n, 3, 0, map), X.device)
+    c = pot._c()
+    _check(lib().smx_triplet_energy(xp, n, ldx, ctypes.byref(c), _map(map), _ptr(E), _ptr(ws), ws.numel(),
+                                    _ptr(s), _stream()))
+    return (E, s) if stats else E
+
+
+def triplet_energy_grad(X: torch.Tensor, pot: Pot = Pot(), map="lambda", ws=None):
+    """(E FP64 [3], dE/dX FP32 [n, 3]) in one pass."""
+    xp, n, ldx = _xarg(X)
+    E = torch.empty(3, dtype=torch.float64, device=X.device)
+    G = torch.empty((n, 3), dtype=torch.float32, device=X.device)
+    ws = ws if ws is not None else _ws(workspace_bytes(2, n, 3, 0, map), X.device)
+    c = pot._c()
+    _check(lib().smx_triplet_energy_grad(xp, n, ldx, ctypes.byref(c), _map(map), _ptr(E), _ptr(G), _ptr(ws),
+                                         ws.numel(), _stream()))
+    return E, G
+
+
+def triplet_energy_backward(X: torch.Tensor, gradE: torch.Tensor, pot: Pot = Pot(), map="lambda", ws=None):
+    """gradE * dE/dX (FP32 [n, 3]); gradE is an FP64 GPU scalar."""
+    xp, n, ldx = _xarg(X)
+    g = gradE.to(torch.float64).reshape(1).contiguous()
+    dX = torch.empty((n, 3), dtype=torch.float32, device=X.device)
+    ws = ws if ws is not None else _ws(workspace_bytes(2, n, 3, 0, map), X.device)
+    c = pot._c()
+    _check(lib().smx_triplet_energy_backward(xp, n, ldx, ctypes.byref(c), _map(map), _dev(g, "gradE"),
+                                             _ptr(dX), _ptr(ws), ws.numel(), _stream()))
+    return dX
+
+
+class TripletEnergy(torch.autograd.Function):
+    """E(X) = Axilrod-Teller (+ Lennard-Jones) energy, FP64 0-d tensor.
+
+    fused=True: the forward pass computes the energy and its gradient in one
+    kernel pass and the backward pass scales the saved gradient;
+    fused=False: the forward pass computes only the energy and the backward
+    pass recomputes the pair terms (smx_triplet_energy_backward).
+    Forces are -dE/dX.
+    """
+
+    @staticmethod
+    def forward(ctx, X, pot: Pot = Pot(), map="lambda", fused: bool = True):
+        ctx.pot, ctx.map, ctx.fused = pot, map, fused
+        if fused and X.requires_grad:
+            E, G = triplet_energy_grad(X.detach(), pot, map)
+            ctx.save_for_backward(G)
+        else:
+            E = triplet_energy(X.detach(), pot, map)
+            ctx.save_for_backward(X.detach())
+        return E[0]
+
+    @staticmethod
+    def backward(ctx, gE):
+        (saved,) = ctx.saved_tensors
+        if ctx.fused:
+            g = gE.detach().to(torch.float64).reshape(1).contiguous()
+            dX = torch.empty_like(saved)
+            _check(lib().smx_scale_grad(_dev(saved, "G"), saved.shape[0], _dev(g, "gradE"), _ptr(dX),
+                                        _stream()))
+        else:
+            dX = triplet_energy_backward(saved, gE.detach(), ctx.pot, ctx.map)
+        return dX, None, None, None
+
+
+# ---------------------------------------------------------------- timing
+def profile_enable(on: bool = True) -> None:
+    _check(lib().smx_profile_enable(int(on)))
+
+
+def profile_reset() -> None:
+    _check(lib().smx_profile_reset())
+
+
+def profile_read(kernel: str):
+    """(total ms, launches) of a kernel since the last reset (synchronises)."""
+    ms, cnt = _dbl(0.0), _i64(0)
+    _check(lib().smx_profile_read(KERNELS[kernel], ctypes.byref(ms), ctypes.byref(cnt)))
+    return ms.value, cnt.value

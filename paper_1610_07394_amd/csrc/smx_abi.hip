@@ -1,0 +1,407 @@
+// C ABI of libsmx: argument validation, workspace layout, and the sequence
+// of kernel launches behind each entry point.  Everything is enqueued on the
+// caller's stream; nothing here allocates device memory or synchronises
+// (except the explicit timing read-out).
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <mutex>
+#include <vector>
+
+#include "smx_device.h"
+#include "smx_internal.h"
+
+namespace smx {
+
+static thread_local char g_err[512] = "";
+
+int fail(int code, const char *fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+    return code;
+}
+
+int check_launch(const char *what) {
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(SMX_EHIP, "%s: launch failed: %s", what, hipGetErrorString(e));
+    return SMX_OK;
+}
+
+// ------------------------------------------------------------------ timing
+namespace {
+struct Rec {
+    int kid;
+    hipEvent_t a, b;
+};
+std::mutex g_mu;
+bool g_prof = false;
+std::vector<Rec> g_pending;
+hipEvent_t g_open[K_COUNT] = {};
+double g_tot[K_COUNT] = {};
+int64_t g_cnt[K_COUNT] = {};
+}  // namespace
+
+void prof_begin(int kid, hipStream_t s) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    if (!g_prof) return;
+    hipEvent_t a;
+    if (hipEventCreate(&a) != hipSuccess) return;
+    hipEventRecord(a, s);
+    g_open[kid] = a;
+}
+
+void prof_end(int kid, hipStream_t s) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    if (!g_prof || g_open[kid] == nullptr) return;
+    hipEvent_t b;
+    if (hipEventCreate(&b) != hipSuccess) return;
+    hipEventRecord(b, s);
+    g_pending.push_back({kid, g_open[kid], b});
+    g_open[kid] = nullptr;
+}
+
+static void prof_collect() {
+    for (const Rec &r : g_pending) {
+        float ms = 0.f;
+        hipEventSynchronize(r.b);
+        if (hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
+            g_tot[r.kid] += ms;
+            g_cnt[r.kid] += 1;
+        }
+        hipEventDestroy(r.a);
+        hipEventDestroy(r.b);
+    }
+    g_pending.clear();
+}
+
+// ------------------------------------------------------------------ geometry
+static bool pow2(int64_t v) { return v > 0 && (v & (v - 1)) == 0; }
+
+static constexpr uint64_t kMaxBlocks = (uint64_t(1) << 31) - 1;
+static constexpr int64_t kMaxN = (int64_t(1) << 31) - 1;
+static constexpr int64_t kMaxGridDim = 65535;
+
+bool make_geom(int m, int64_t nb, int map, MapGeom &g) {
+    memset(&g, 0, sizeof(g));
+    g.nb = int32_t(nb);
+    g.map = uint32_t(map);
+    const uint64_t u = uint64_t(nb);
+    if (map == MAP_LAMBDA) {
+        g.lg = ceil_log2_u64(u);
+        if (g.lg > 30) return fail(SMX_EOVERFLOW, "lambda grid too large (nb = %lld)", (long long)nb), false;
+        const uint64_t g2 = lambda2_blocks(g.lg);
+        if (m == 2) {
+            g.G = g2;
+        } else {
+            if (g.lg > 21) return fail(SMX_EOVERFLOW, "lambda3 grid too large (nb = %lld)", (long long)nb), false;
+            const uint64_t half = g.lg == 0 ? 0 : (uint64_t(1) << (g.lg - 1));
+            const uint64_t main = half * half * (half + half / 2);
+            if (main > kMaxBlocks) return fail(SMX_EOVERFLOW, "lambda3 grid too large"), false;
+            g.main = uint32_t(main);
+            g.G = main + g2;
+        }
+    } else if (map == MAP_BBOX) {
+        if (nb > kMaxGridDim) return fail(SMX_EUNSUPPORTED, "bounding-box grid dimension %lld > 65535", (long long)nb), false;
+        g.G = m == 2 ? u * u : u * u * u;
+    } else {
+        g.G = m == 2 ? u * (u + 1) / 2 : u * (u + 1) * (u + 2) / 6;
+    }
+    if (g.G > kMaxBlocks) return fail(SMX_EOVERFLOW, "parallel space of %llu blocks exceeds 2^31 - 1", (unsigned long long)g.G), false;
+    return true;
+}
+
+static int check_common(int m, int64_t n, int rho, int map, int maxrho) {
+    if (m != 2 && m != 3) return fail(SMX_EINVAL, "m must be 2 or 3 (got %d)", m);
+    if (n < 0) return fail(SMX_EINVAL, "n must be >= 0 (got %lld)", (long long)n);
+    if (n > kMaxN) return fail(SMX_EOVERFLOW, "n = %lld exceeds 2^31 - 1", (long long)n);
+    if (!pow2(rho) || rho > maxrho) return fail(SMX_EINVAL, "rho must be a power of two in [1, %d] (got %d)", maxrho, rho);
+    if (map < 0 || map > 2) return fail(SMX_EINVAL, "unknown map %d", map);
+    return SMX_OK;
+}
+
+static inline size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
+
+// Workspace layouts.
+struct EdmWs {
+    size_t slots, hi, lo, norms, total;
+};
+static EdmWs edm_ws(int64_t n, int64_t d, int prec) {
+    EdmWs w{};
+    w.slots = 0;
+    size_t off = kSlotBytes;
+    if (prec != SMX_EDM_FP32_DIFF) {
+        const int64_t dpad = (d + kGramK - 1) / kGramK * kGramK;
+        w.hi = off;
+        off = align256(off + size_t(n) * size_t(dpad) * 2);
+        w.lo = off;
+        if (prec == SMX_EDM_SPLITBF16_GRAM) off = align256(off + size_t(n) * size_t(dpad) * 2);
+        w.norms = off;
+        off = align256(off + size_t(n) * 4);
+    }
+    w.total = off;
+    return w;
+}
+
+struct TripWs {
+    size_t eslots, at_stats, lj_stats, g64, total;
+};
+static TripWs trip_ws(int64_t n) {
+    TripWs w{};
+    w.eslots = 0;
+    w.at_stats = kSlotBytes;
+    w.lj_stats = 2 * kSlotBytes;
+    w.g64 = 3 * kSlotBytes;
+    w.total = align256(w.g64 + size_t(n) * 3 * 8);
+    return w;
+}
+
+static inline hipStream_t S(void *s) { return reinterpret_cast<hipStream_t>(s); }
+
+}  // namespace smx
+
+using namespace smx;
+
+extern "C" {
+
+const char *smx_version(void) { return "smx 0.1 (gfx950)"; }
+
+const char *smx_last_error(void) { return g_err; }
+
+int64_t smx_volume(int m, int64_t n, int strict) {
+    if ((m != 2 && m != 3) || n < 0 || n > kMaxN) return -1;
+    const __int128 a = n, b = strict ? n - 1 : n + 1;
+    __int128 v;
+    if (m == 2) v = a * b / 2;
+    else v = strict ? a * (n - 1) * (n - 2) / 6 : a * (n + 1) * (n + 2) / 6;
+    if (v < 0) v = 0;
+    if (v > (__int128)INT64_MAX) return -1;
+    return int64_t(v);
+}
+
+int64_t smx_parallel_blocks(int m, int64_t n, int rho, int map) {
+    if (check_common(m, n, rho, map, m == 2 ? 1024 : 64) != SMX_OK) return -1;
+    if (n == 0) return 0;
+    MapGeom g;
+    if (!make_geom(m, (n + rho - 1) / rho, map, g)) return -1;
+    return int64_t(g.G);
+}
+
+size_t smx_workspace_bytes(int op, int64_t n, int64_t d, int prec, int map) {
+    (void)map;
+    if (n < 0 || n > kMaxN) return 0;
+    if (op == 0) return kSlotBytes;
+    if (op == 1) {
+        if (d < 1 || prec < 0 || prec > 2) return 0;
+        return edm_ws(n, d, prec).total;
+    }
+    if (op == 2) return trip_ws(n).total;
+    return 0;
+}
+
+int smx_map_tiles_host(int m, int64_t n, int rho, int map, int64_t first, int64_t count, int32_t *tiles) {
+    int rc = check_common(m, n, rho, map, m == 2 ? 1024 : 64);
+    if (rc != SMX_OK) return rc;
+    if (count < 0 || first < 0) return fail(SMX_EINVAL, "negative block range");
+    if (count == 0) return SMX_OK;
+    if (tiles == nullptr) return fail(SMX_EINVAL, "tiles is NULL");
+    MapGeom g;
+    if (n == 0 || !make_geom(m, (n + rho - 1) / rho, map, g)) return n == 0 ? fail(SMX_EINVAL, "n = 0 launches no blocks") : SMX_EOVERFLOW;
+    if (uint64_t(first) + uint64_t(count) > g.G) return fail(SMX_EINVAL, "block range past the parallel space");
+    for (uint64_t b = uint64_t(first); b < uint64_t(first + count); ++b) {
+        int X = -1, Y = -1, Z = -1;
+        int32_t *o = tiles + (b - uint64_t(first)) * m;
+        bool ok;
+        if (m == 2) {
+            if (map == MAP_LAMBDA) ok = lambda2(uint32_t(b), g.lg, g.nb, X, Y);
+            else if (map == MAP_BBOX) { X = int(b % g.nb); Y = int(b / g.nb); ok = X <= Y; }
+            else { linear2(uint32_t(b), X, Y); ok = true; }
+            o[0] = ok ? X : -1;
+            o[1] = ok ? Y : -1;
+        } else {
+            if (map == MAP_LAMBDA) ok = lambda3(uint32_t(b), g.lg, g.nb, g.main, X, Y, Z);
+            else if (map == MAP_BBOX) {
+                X = int(b % g.nb); Y = int((b / g.nb) % g.nb); Z = int(b / (uint64_t(g.nb) * g.nb));
+                ok = X <= Y && Y <= Z;
+            } else { linear3(uint32_t(b), X, Y, Z); ok = true; }
+            o[0] = ok ? X : -1;
+            o[1] = ok ? Y : -1;
+            o[2] = ok ? Z : -1;
+        }
+    }
+    return SMX_OK;
+}
+
+static int map_dump(int m, int64_t n, int rho, int map, int strict, int32_t *d_tiles, int64_t *d_stats,
+                    void *d_ws, size_t ws_bytes, void *stream) {
+    int rc = check_common(m, n, rho, map, m == 2 ? 1024 : 64);
+    if (rc != SMX_OK) return rc;
+    if (d_stats != nullptr && (d_ws == nullptr || ws_bytes < kSlotBytes))
+        return fail(SMX_EINVAL, "statistics need a workspace of %zu bytes", kSlotBytes);
+    if (n == 0) return SMX_OK;
+    MapGeom g;
+    if (!make_geom(m, (n + rho - 1) / rho, map, g)) return SMX_EOVERFLOW;
+    unsigned long long *slots = d_stats ? reinterpret_cast<unsigned long long *>(d_ws) : nullptr;
+    if (slots && (rc = launch_fill_u64(reinterpret_cast<uint64_t *>(slots), kSlotBytes / 8, S(stream))))
+        return rc;
+    rc = m == 2 ? launch_map2(g, n, rho, map, strict, d_tiles, slots, S(stream))
+                : launch_map3(g, n, rho, map, strict, d_tiles, slots, S(stream));
+    if (rc) return rc;
+    if (slots) return launch_stats_finalize(slots, g.G, d_stats, S(stream));
+    return SMX_OK;
+}
+
+int smx_simplex_map2(int64_t n, int rho, int map, int strict, int32_t *d_tiles, int64_t *d_stats,
+                     void *d_ws, size_t ws_bytes, void *stream) {
+    return map_dump(2, n, rho, map, strict, d_tiles, d_stats, d_ws, ws_bytes, stream);
+}
+
+int smx_simplex_map3(int64_t n, int rho, int map, int strict, int32_t *d_tiles, int64_t *d_stats,
+                     void *d_ws, size_t ws_bytes, void *stream) {
+    return map_dump(3, n, rho, map, strict, d_tiles, d_stats, d_ws, ws_bytes, stream);
+}
+
+int smx_edm_packed(const float *d_X, int64_t n, int64_t d, int64_t ldx, int map, int prec, float *d_D,
+                   void *d_ws, size_t ws_bytes, int64_t *d_stats, void *stream) {
+    if (n < 0) return fail(SMX_EINVAL, "n must be >= 0");
+    if (n > kMaxN) return fail(SMX_EOVERFLOW, "n exceeds 2^31 - 1");
+    if (d < 1) return fail(SMX_EINVAL, "d must be >= 1 (got %lld)", (long long)d);
+    if (ldx < d) return fail(SMX_EINVAL, "ldx (%lld) < d (%lld)", (long long)ldx, (long long)d);
+    if (map < 0 || map > 2) return fail(SMX_EINVAL, "unknown map %d", map);
+    if (prec < 0 || prec > 2) return fail(SMX_EINVAL, "unknown precision %d", prec);
+    if (n == 0) return SMX_OK;
+    if (d_X == nullptr || d_D == nullptr) return fail(SMX_EINVAL, "X and D must not be NULL");
+    const EdmWs w = edm_ws(n, d, prec);
+    const bool need_ws = prec != SMX_EDM_FP32_DIFF || d_stats != nullptr;
+    if (need_ws && (d_ws == nullptr || ws_bytes < w.total))
+        return fail(SMX_EINVAL, "workspace of %zu bytes required (got %zu)", w.total, ws_bytes);
+    const int tile = prec == SMX_EDM_FP32_DIFF ? kEdmTile : kGramTile;
+    MapGeom g;
+    if (!make_geom(2, (n + tile - 1) / tile, map, g)) return SMX_EOVERFLOW;
+    char *ws = reinterpret_cast<char *>(d_ws);
+    unsigned long long *slots = d_stats ? reinterpret_cast<unsigned long long *>(ws + w.slots) : nullptr;
+    int rc;
+    if (slots && (rc = launch_fill_u64(reinterpret_cast<uint64_t *>(slots), kSlotBytes / 8, S(stream))))
+        return rc;
+    if (prec == SMX_EDM_FP32_DIFF) {
+        rc = launch_edm_diff(g, d_X, n, d, ldx, d_D, slots, S(stream));
+    } else {
+        const bool split = prec == SMX_EDM_SPLITBF16_GRAM;
+        const int64_t dpad = (d + kGramK - 1) / kGramK * kGramK;
+        uint16_t *hi = reinterpret_cast<uint16_t *>(ws + w.hi);
+        uint16_t *lo = reinterpret_cast<uint16_t *>(ws + w.lo);
+        float *norms = reinterpret_cast<float *>(ws + w.norms);
+        rc = launch_gram_prep(d_X, n, d, ldx, dpad, hi, lo, norms, split, S(stream));
+        if (rc == SMX_OK) rc = launch_edm_gram(g, hi, lo, norms, n, dpad, split, d_D, slots, S(stream));
+    }
+    if (rc) return rc;
+    if (slots) return launch_stats_finalize(slots, g.G, d_stats, S(stream));
+    return SMX_OK;
+}
+
+static int check_pot(const smx_pot *pot) {
+    if (pot == nullptr) return fail(SMX_EINVAL, "pot is NULL");
+    if (pot->lj_on && !(pot->lj_rc > 0.0 && pot->lj_sigma > 0.0))
+        return fail(SMX_EINVAL, "LJ needs sigma > 0 and rc > 0");
+    return SMX_OK;
+}
+
+// Shared body of the triplet calls.  mode 0: energy; 1: energy + gradient;
+// 2: backward (gradient scaled by *d_gradE).
+static int triplet_run(int mode, const float *d_X, int64_t n, int64_t ldx, const smx_pot *pot, int map,
+                       double *d_E, float *d_G, const double *d_gradE, void *d_ws, size_t ws_bytes,
+                       int64_t *d_stats, void *stream) {
+    if (n < 0) return fail(SMX_EINVAL, "n must be >= 0");
+    if (n > kMaxN) return fail(SMX_EOVERFLOW, "n exceeds 2^31 - 1");
+    if (ldx < 3) return fail(SMX_EINVAL, "ldx must be >= 3 (got %lld)", (long long)ldx);
+    if (map < 0 || map > 2) return fail(SMX_EINVAL, "unknown map %d", map);
+    int rc = check_pot(pot);
+    if (rc) return rc;
+    if (mode == 0 && d_E == nullptr) return fail(SMX_EINVAL, "E must not be NULL");
+    if (mode >= 1 && n > 0 && d_G == nullptr) return fail(SMX_EINVAL, "gradient output must not be NULL");
+    if (mode == 2 && d_gradE == nullptr) return fail(SMX_EINVAL, "gradE must not be NULL");
+    if (n > 0 && d_X == nullptr) return fail(SMX_EINVAL, "X must not be NULL");
+    const TripWs w = trip_ws(n);
+    if (d_ws == nullptr || ws_bytes < w.total)
+        return fail(SMX_EINVAL, "workspace of %zu bytes required (got %zu)", w.total, ws_bytes);
+    MapGeom g3, g2;
+    const int64_t nb3 = (n + kTripTile - 1) / kTripTile, nb2 = (n + kLjTile - 1) / kLjTile;
+    const bool do_at = pot->at_on && n >= 3, do_lj = pot->lj_on && n >= 2;
+    if (do_at && !make_geom(3, nb3, map, g3)) return SMX_EOVERFLOW;
+    if (do_lj && !make_geom(2, nb2, map, g2)) return SMX_EOVERFLOW;
+
+    char *ws = reinterpret_cast<char *>(d_ws);
+    double *eslots = reinterpret_cast<double *>(ws + w.eslots);
+    unsigned long long *at_st = d_stats ? reinterpret_cast<unsigned long long *>(ws + w.at_stats) : nullptr;
+    unsigned long long *lj_st = d_stats ? reinterpret_cast<unsigned long long *>(ws + w.lj_stats) : nullptr;
+    double *G64 = reinterpret_cast<double *>(ws + w.g64);
+    hipStream_t s = S(stream);
+    // zero energy slots, statistics slots and the FP64 gradient in one fill
+    const size_t zero_words = (mode == 0 ? (d_stats ? w.g64 : w.at_stats) : w.total) / 8;
+    if ((rc = launch_fill_u64(reinterpret_cast<uint64_t *>(ws), zero_words, s))) return rc;
+    const bool grad = mode >= 1;
+    if (do_at && (rc = launch_triplet(g3, d_X, n, ldx, float(pot->nu), grad, G64, eslots, at_st, s))) return rc;
+    if (do_lj && (rc = launch_lj(g2, d_X, n, ldx, float(pot->lj_eps), float(pot->lj_sigma),
+                                 float(pot->lj_rc * pot->lj_rc), G64, eslots, lj_st, s)))
+        return rc;
+    if (d_E != nullptr && (rc = launch_energy_finalize(eslots, d_E, s))) return rc;
+    if (d_stats != nullptr) {
+        if ((rc = launch_stats_finalize(at_st, do_at ? g3.G : 0, d_stats, s))) return rc;
+        if ((rc = launch_stats_finalize(lj_st, do_lj ? g2.G : 0, d_stats + 4, s))) return rc;
+    }
+    if (grad && n > 0 && (rc = launch_grad_finalize(G64, n, mode == 2 ? d_gradE : nullptr, d_G, s))) return rc;
+    return SMX_OK;
+}
+
+int smx_triplet_energy(const float *d_X, int64_t n, int64_t ldx, const smx_pot *pot, int map, double *d_E,
+                       void *d_ws, size_t ws_bytes, int64_t *d_stats, void *stream) {
+    return triplet_run(0, d_X, n, ldx, pot, map, d_E, nullptr, nullptr, d_ws, ws_bytes, d_stats, stream);
+}
+
+int smx_triplet_energy_grad(const float *d_X, int64_t n, int64_t ldx, const smx_pot *pot, int map,
+                            double *d_E, float *d_G, void *d_ws, size_t ws_bytes, void *stream) {
+    return triplet_run(1, d_X, n, ldx, pot, map, d_E, d_G, nullptr, d_ws, ws_bytes, nullptr, stream);
+}
+
+int smx_triplet_energy_backward(const float *d_X, int64_t n, int64_t ldx, const smx_pot *pot, int map,
+                                const double *d_gradE, float *d_dX, void *d_ws, size_t ws_bytes,
+                                void *stream) {
+    return triplet_run(2, d_X, n, ldx, pot, map, nullptr, d_dX, d_gradE, d_ws, ws_bytes, nullptr, stream);
+}
+
+int smx_scale_grad(const float *d_G, int64_t n, const double *d_gradE, float *d_out, void *stream) {
+    if (n < 0) return fail(SMX_EINVAL, "n must be >= 0");
+    if (n > kMaxN) return fail(SMX_EOVERFLOW, "n exceeds 2^31 - 1");
+    if (n == 0) return SMX_OK;
+    if (d_G == nullptr || d_gradE == nullptr || d_out == nullptr) return fail(SMX_EINVAL, "NULL argument");
+    return launch_scale_grad(d_G, n, d_gradE, d_out, S(stream));
+}
+
+int smx_profile_enable(int on) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_prof = on != 0;
+    return SMX_OK;
+}
+
+int smx_profile_reset(void) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    prof_collect();
+    for (int k = 0; k < K_COUNT; ++k) {
+        g_tot[k] = 0.0;
+        g_cnt[k] = 0;
+    }
+    return SMX_OK;
+}
+
+int smx_profile_read(int kernel_id, double *total_ms, int64_t *launches) {
+    if (kernel_id < 0 || kernel_id >= K_COUNT) return fail(SMX_EINVAL, "unknown kernel id %d", kernel_id);
+    std::lock_guard<std::mutex> lk(g_mu);
+    prof_collect();
+    if (total_ms) *total_ms = g_tot[kernel_id];
+    if (launches) *launches = g_cnt[kernel_id];
+    return SMX_OK;
+}
+
+}  // extern "C"

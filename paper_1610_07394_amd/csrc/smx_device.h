@@ -1,0 +1,96 @@
+// Device-side helpers shared by the kernels: launch geometry, element ids,
+// SplitMix64, wave64 reductions and the statistics / energy slots.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "smx_maps.h"
+
+namespace smx {
+
+constexpr int kWave = 64;
+// Statistics and energy partials are accumulated with atomics spread over
+// kSlots addresses, one 128-byte line apart, so that millions of blocks do not
+// serialise on one address.  A finalize kernel sums the slots.
+constexpr int kSlots = 256;
+constexpr int kSlotStride = 16;  // 16 x 8 bytes = one 128-byte line
+constexpr size_t kSlotBytes = size_t(kSlots) * kSlotStride * 8;
+
+// Logical index of this block on a 1-D or 2-D launch of G blocks (2-D when
+// G * threads would overflow the 32-bit per-dimension thread count).
+__device__ __forceinline__ uint64_t launch_index() {
+    return uint64_t(blockIdx.y) * gridDim.x + blockIdx.x;
+}
+
+// SplitMix64 finaliser (Steele, Lea, Flood, OOPSLA 2014): the output function
+// applied to state x + golden-ratio increment.
+__device__ __forceinline__ uint64_t mix64(uint64_t x) {
+    uint64_t z = x + 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+// Element ids (bijections onto [0, V)).
+__device__ __forceinline__ uint64_t id_pair_le(uint64_t i, uint64_t j, uint64_t n) {
+    return i * n - (i * (i - 1)) / 2 + (j - i);  // i = 0: (0 * -1) / 2 wraps to 0 correctly
+}
+__device__ __forceinline__ uint64_t id_pair_lt(uint64_t i, uint64_t j) { return (j * (j - 1)) / 2 + i; }
+__device__ __forceinline__ uint64_t id_trip_le(uint64_t i, uint64_t j, uint64_t k) {
+    return (k * (k + 1) * (k + 2)) / 6 + (j * (j + 1)) / 2 + i;
+}
+__device__ __forceinline__ uint64_t id_trip_lt(uint64_t i, uint64_t j, uint64_t k) {
+    return (k * (k - 1) * (k - 2)) / 6 + (j * (j - 1)) / 2 + i;
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
+    return v;
+}
+
+// Block-wide sum of a per-thread value; the result is valid in thread 0.
+template <typename T, int NTHREADS>
+__device__ __forceinline__ T block_sum(T v, T *scratch /* NTHREADS / 64 entries */) {
+    v = wave_sum(v);
+    const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+    if (lane == 0) scratch[wid] = v;
+    __syncthreads();
+    T r = T(0);
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int w = 0; w < NTHREADS / kWave; ++w) r += scratch[w];
+    }
+    return r;
+}
+
+// Count and checksum the pairs i <= j (ids p(i, j), the packed index) of the
+// tile rows [i0, i0 + rows) x columns [j0, j0 + cols), all threads of the block
+// taking part.  Used by the statistics variants of the EDM kernels, after the
+// tile is stored, so that the counting does not share registers with the tile
+// arithmetic.
+template <int NTHREADS>
+__device__ __forceinline__ void tile_pairs_le_stats(int64_t i0, int64_t j0, int rows, int cols, int64_t n,
+                                                    unsigned long long &cnt, unsigned long long &cs) {
+    cnt = 0;
+    cs = 0;
+    for (int e = threadIdx.x; e < rows * cols; e += NTHREADS) {
+        const int64_t i = i0 + e / cols, j = j0 + e % cols;
+        if (j < n && i <= j) {
+            ++cnt;
+            cs += mix64(id_pair_le(uint64_t(i), uint64_t(j), uint64_t(n)));
+        }
+    }
+}
+
+// Statistics slot layout: [slot * kSlotStride + {0: elements, 1: checksum, 2: mapped blocks}]
+__device__ __forceinline__ void stats_add(unsigned long long *slots, uint64_t blk, uint64_t elems,
+                                          uint64_t csum) {
+    unsigned long long *s = slots + (blk % kSlots) * kSlotStride;
+    atomicAdd(s + 0, (unsigned long long)elems);
+    atomicAdd(s + 1, (unsigned long long)csum);
+    atomicAdd(s + 2, 1ull);
+}
+
+}  // namespace smx

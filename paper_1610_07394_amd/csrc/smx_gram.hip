@@ -1,0 +1,247 @@
+// Packed Euclidean distance matrix, Gram form on the BF16 matrix cores.
+//
+//   D_ij = |x_i|^2 + |x_j|^2 - 2 G_ij,  G = X X^T on the tile pair (I, J),
+//
+// with G from v_mfma_f32_32x32x16_bf16 (FP32 accumulation) and the norms in
+// FP32 from the FP32 input.  Plain BF16: G = hi hi^T.  Split BF16 (hi =
+// bf16(x), lo = bf16(x - hi), both round-to-nearest-even): G = hi hi^T +
+// hi lo^T + lo hi^T, dropping lo lo^T (relative size 2^-16).  D is clamped
+// at 0 and the diagonal is set to exactly 0 (the Gram form cancels there).
+//
+// Block: 256 threads (4 waves as 2 x 2), tile 128 x 128 of the packed upper
+// triangle, each wave 64 x 64 = 2 x 2 MFMA tiles of 32 x 32.  K advances in
+// chunks of 32 through LDS (row-major, row stride 40 bf16 = 80 bytes so the
+// 16-byte fragment reads of 16 consecutive rows hit distinct bank groups), with
+// the next chunk prefetched into registers while the matrix cores run.
+#include "smx_device.h"
+#include "smx_internal.h"
+
+namespace smx {
+
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+typedef float f32x16_t __attribute__((ext_vector_type(16)));
+
+constexpr int kGramThreads = 256;
+constexpr int kGramLd = kGramK + 8;  // 40 bf16 per LDS row
+
+__device__ __forceinline__ uint16_t bf16_rne(float f) {
+    uint32_t u = __float_as_uint(f);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return uint16_t((u >> 16) | 0x40u);  // quiet NaN
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return uint16_t(u >> 16);
+}
+
+__device__ __forceinline__ float bf16_to_f32(uint16_t h) { return __uint_as_float(uint32_t(h) << 16); }
+
+// One wave per row: hi / lo BF16 copies (zero padded to dpad) and the FP32
+// squared norm sum_k x_k^2 (lane-strided FMA sums, then a fixed wave tree).
+__global__ __launch_bounds__(256) void gram_prep_kernel(const float *__restrict__ X, int64_t n,
+                                                        int64_t d, int64_t ldx, int64_t dpad,
+                                                        uint16_t *__restrict__ hi,
+                                                        uint16_t *__restrict__ lo,
+                                                        float *__restrict__ norms) {
+    const int lane = threadIdx.x & 63;
+    const int64_t row = int64_t(blockIdx.x) * 4 + (threadIdx.x >> 6);
+    if (row >= n) return;
+    float acc = 0.f;
+    for (int64_t k = lane; k < dpad; k += 64) {
+        const float x = k < d ? X[row * ldx + k] : 0.f;
+        acc = __builtin_fmaf(x, x, acc);
+        const uint16_t h = bf16_rne(x);
+        hi[row * dpad + k] = h;
+        if (lo != nullptr) lo[row * dpad + k] = bf16_rne(x - bf16_to_f32(h));
+    }
+    acc = wave_sum(acc);
+    if (lane == 0) norms[row] = acc;
+}
+
+int launch_gram_prep(const float *X, int64_t n, int64_t d, int64_t ldx, int64_t dpad, uint16_t *hi,
+                     uint16_t *lo, float *norms, bool split, hipStream_t s) {
+    prof_begin(K_GRAM_PREP, s);
+    hipLaunchKernelGGL(gram_prep_kernel, dim3(uint32_t((n + 3) / 4)), dim3(256), 0, s, X, n, d, ldx,
+                       dpad, hi, split ? lo : nullptr, norms);
+    prof_end(K_GRAM_PREP, s);
+    return check_launch("gram prep");
+}
+
+template <int MAP>
+__device__ __forceinline__ bool gram_tile(const MapGeom &g, uint64_t &lin, int &X, int &Y) {
+    if (MAP == MAP_BBOX) {
+        X = int(blockIdx.x);
+        Y = int(blockIdx.y);
+        lin = uint64_t(Y) * uint64_t(g.nb) + uint64_t(X);
+        return X <= Y;
+    }
+    lin = launch_index();
+    if (lin >= g.G) return false;
+    const uint32_t id = xcd_remap(uint32_t(lin), uint32_t(g.G));
+    lin = id;
+    if (MAP == MAP_LAMBDA) return lambda2(id, g.lg, g.nb, X, Y);
+    linear2(id, X, Y);
+    return true;
+}
+
+// Global -> register staging of one K chunk: this thread's 16 bf16 (32 bytes)
+// of row ra_row (I panel) and rb_row (J panel), for hi and, when split, lo.
+template <int NP>
+__device__ __forceinline__ void gram_gload(uint4 (&ra)[NP][2], uint4 (&rb)[NP][2], const uint16_t *__restrict__ hi,
+                                           const uint16_t *__restrict__ lo, int64_t ra_row, int64_t rb_row,
+                                           int64_t n, int64_t dpad, int64_t kofs) {
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+        const uint16_t *src = p == 0 ? hi : lo;
+        ra[p][0] = ra[p][1] = make_uint4(0, 0, 0, 0);
+        rb[p][0] = rb[p][1] = make_uint4(0, 0, 0, 0);
+        if (ra_row < n) {
+            const uint4 *q = reinterpret_cast<const uint4 *>(src + ra_row * dpad + kofs);
+            ra[p][0] = q[0];
+            ra[p][1] = q[1];
+        }
+        if (rb_row < n) {
+            const uint4 *q = reinterpret_cast<const uint4 *>(src + rb_row * dpad + kofs);
+            rb[p][0] = q[0];
+            rb[p][1] = q[1];
+        }
+    }
+}
+
+template <int MAP, bool SPLIT, bool STATS>
+__global__ __launch_bounds__(kGramThreads) void edm_gram_kernel(MapGeom g, const uint16_t *__restrict__ hi,
+                                                               const uint16_t *__restrict__ lo,
+                                                               const float *__restrict__ norms,
+                                                               int64_t n, int64_t dpad,
+                                                               float *__restrict__ D,
+                                                               unsigned long long *slots) {
+    uint64_t lin;
+    int TX, TY;
+    if (!gram_tile<MAP>(g, lin, TX, TY)) return;
+    constexpr int NP = SPLIT ? 2 : 1;
+    __shared__ __attribute__((aligned(16))) uint16_t As[NP][kGramTile * kGramLd];
+    __shared__ __attribute__((aligned(16))) uint16_t Bs[NP][kGramTile * kGramLd];
+    __shared__ float nA[kGramTile], nB[kGramTile];
+
+    const int t = threadIdx.x;
+    const int lane = t & 63, w = t >> 6, wm = w >> 1, wn = w & 1;
+    const int64_t I0 = int64_t(TX) * kGramTile, J0 = int64_t(TY) * kGramTile;
+    const bool diag = TX == TY;
+
+    if (t < kGramTile) nA[t] = I0 + t < n ? norms[I0 + t] : 0.f;
+    else nB[t - kGramTile] = J0 + t - kGramTile < n ? norms[J0 + t - kGramTile] : 0.f;
+
+    // global -> register staging: thread owns 16 bf16 (32 bytes) of one row
+    const int lrow = t >> 1, lhalf = t & 1;
+    const int64_t ra_row = I0 + lrow, rb_row = J0 + lrow;
+    uint4 ra[NP][2], rb[NP][2];
+
+    f32x16_t acc[2][2];
+#pragma unroll
+    for (int m = 0; m < 2; ++m)
+#pragma unroll
+        for (int c = 0; c < 2; ++c)
+#pragma unroll
+            for (int e = 0; e < 16; ++e) acc[m][c][e] = 0.f;
+
+    gram_gload<NP>(ra, rb, hi, lo, ra_row, rb_row, n, dpad, 16 * lhalf);
+    for (int64_t k0 = 0; k0 < dpad; k0 += kGramK) {
+#pragma unroll
+        for (int p = 0; p < NP; ++p) {
+            uint4 *a = reinterpret_cast<uint4 *>(&As[p][lrow * kGramLd + 16 * lhalf]);
+            uint4 *b = reinterpret_cast<uint4 *>(&Bs[p][lrow * kGramLd + 16 * lhalf]);
+            a[0] = ra[p][0];
+            a[1] = ra[p][1];
+            b[0] = rb[p][0];
+            b[1] = rb[p][1];
+        }
+        __syncthreads();
+        if (k0 + kGramK < dpad) gram_gload<NP>(ra, rb, hi, lo, ra_row, rb_row, n, dpad, k0 + kGramK + 16 * lhalf);
+#pragma unroll
+        for (int ks = 0; ks < kGramK / 16; ++ks) {
+            const int kofs = ks * 16 + 8 * (lane >> 5);
+            bf16x8_t a[NP][2], b[NP][2];
+#pragma unroll
+            for (int p = 0; p < NP; ++p)
+#pragma unroll
+                for (int m = 0; m < 2; ++m) {
+                    a[p][m] = *reinterpret_cast<const bf16x8_t *>(
+                        &As[p][(wm * 64 + m * 32 + (lane & 31)) * kGramLd + kofs]);
+                    b[p][m] = *reinterpret_cast<const bf16x8_t *>(
+                        &Bs[p][(wn * 64 + m * 32 + (lane & 31)) * kGramLd + kofs]);
+                }
+#pragma unroll
+            for (int m = 0; m < 2; ++m)
+#pragma unroll
+                for (int c = 0; c < 2; ++c) {
+                    acc[m][c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[0][m], b[0][c], acc[m][c], 0, 0, 0);
+                    if (SPLIT) {
+                        acc[m][c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[0][m], b[1][c], acc[m][c], 0, 0, 0);
+                        acc[m][c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[1][m], b[0][c], acc[m][c], 0, 0, 0);
+                    }
+                }
+        }
+        __syncthreads();
+    }
+
+    // 32 x 32 accumulator layout: lane l, element e holds row
+    // (e & 3) + 4 (l >> 5) + 8 (e >> 2) and column l & 31 of the MFMA tile.
+#pragma unroll
+    for (int m = 0; m < 2; ++m)
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+            const int il = wm * 64 + m * 32 + (e & 3) + 4 * (lane >> 5) + 8 * (e >> 2);
+            const int64_t i = I0 + il;
+            if (i >= n) continue;
+            const int64_t rowbase = i * n - (i * (i - 1)) / 2 - i;
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                const int jl = wn * 64 + c * 32 + (lane & 31);
+                const int64_t j = J0 + jl;
+                if (j < n && (!diag || j >= i)) {
+                    float v = __builtin_fmaf(-2.f, acc[m][c][e], nA[il] + nB[jl]);
+                    v = (i == j) ? 0.f : fmaxf(v, 0.f);
+                    __builtin_nontemporal_store(v, D + rowbase + j);
+                }
+            }
+        }
+    if (STATS) {
+        __shared__ unsigned long long red[2][kGramThreads / kWave];
+        unsigned long long cnt, cs;
+        tile_pairs_le_stats<kGramThreads>(I0, J0, kGramTile, kGramTile, n, cnt, cs);
+        const unsigned long long c = block_sum<unsigned long long, kGramThreads>(cnt, red[0]);
+        const unsigned long long h = block_sum<unsigned long long, kGramThreads>(cs, red[1]);
+        if (t == 0) stats_add(slots, lin, c, h);
+    }
+}
+
+template <int MAP, bool SPLIT>
+static void go_gram(const MapGeom &g, const uint16_t *hi, const uint16_t *lo, const float *norms,
+                    int64_t n, int64_t dpad, float *D, unsigned long long *slots, hipStream_t s) {
+    const dim3 grid = MAP == MAP_BBOX ? dim3(g.nb, g.nb, 1) : grid_for(g.G, kGramThreads);
+    if (slots)
+        hipLaunchKernelGGL((edm_gram_kernel<MAP, SPLIT, true>), grid, dim3(kGramThreads), 0, s, g, hi, lo,
+                           norms, n, dpad, D, slots);
+    else
+        hipLaunchKernelGGL((edm_gram_kernel<MAP, SPLIT, false>), grid, dim3(kGramThreads), 0, s, g, hi, lo,
+                           norms, n, dpad, D, slots);
+}
+
+int launch_edm_gram(const MapGeom &g, const uint16_t *hi, const uint16_t *lo, const float *norms,
+                    int64_t n, int64_t dpad, bool split, float *D, unsigned long long *slots,
+                    hipStream_t s) {
+    prof_begin(K_EDM_GRAM, s);
+    const int map = int(g.map);
+#define SMX_GO(M)                                                            \
+    if (split) go_gram<M, true>(g, hi, lo, norms, n, dpad, D, slots, s); \
+    else go_gram<M, false>(g, hi, lo, norms, n, dpad, D, slots, s);
+    if (map == MAP_LAMBDA) {
+        SMX_GO(MAP_LAMBDA)
+    } else if (map == MAP_BBOX) {
+        SMX_GO(MAP_BBOX)
+    } else {
+        SMX_GO(MAP_LINEAR)
+    }
+#undef SMX_GO
+    prof_end(K_EDM_GRAM, s);
+    return check_launch("edm_packed (gram)");
+}
+
+}  // namespace smx

@@ -1,0 +1,71 @@
+// Host-side internals shared by the translation units of libsmx.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "smx.h"
+#include "smx_maps.h"
+
+namespace smx {
+
+// Per-thread error message (smx_last_error).
+int fail(int code, const char *fmt, ...);
+// Map a HIP error (if any) to SMX_EHIP with a message.
+int check_launch(const char *what);
+
+// Kernel ids for the timing facility (match smx_profile_read).
+enum KernelId {
+    K_MAP2 = 0, K_MAP3 = 1, K_EDM_DIFF = 2, K_EDM_GRAM = 3, K_GRAM_PREP = 4,
+    K_TRIP_ENERGY = 5, K_TRIP_GRAD = 6, K_LJ = 7, K_FINALIZE = 8, K_COUNT = 9
+};
+void prof_begin(int kid, hipStream_t s);
+void prof_end(int kid, hipStream_t s);
+
+// Grid for G logical blocks of `threads` threads: 1-D when it fits the 32-bit
+// per-dimension thread count, else 2-D with 65536 blocks per row (a multiple
+// of 8, so the XCD of a block stays blockIdx.x mod 8).  Kernels recompute the
+// logical index with launch_index() and drop indices >= G.
+inline dim3 grid_for(uint64_t G, int threads) {
+    if (G * uint64_t(threads) < (uint64_t(1) << 32)) return dim3(uint32_t(G), 1, 1);
+    const uint64_t gx = 65536;
+    return dim3(uint32_t(gx), uint32_t((G + gx - 1) / gx), 1);
+}
+
+// Map geometry for m-dimensional work with nb tiles per dimension.
+// Returns false (with an error set) when the grid does not fit the index types.
+bool make_geom(int m, int64_t nb, int map, MapGeom &g);
+
+// ------------------------------------------------------------------ launchers
+// Each returns SMX_OK or an error code; arguments are already validated.
+int launch_fill_u64(uint64_t *p, size_t count, hipStream_t s);
+int launch_stats_finalize(const unsigned long long *slots, uint64_t launched, int64_t *d_stats,
+                          hipStream_t s);
+
+int launch_map2(const MapGeom &g, int64_t n, int rho, int map, int strict, int32_t *tiles,
+                unsigned long long *slots, hipStream_t s);
+int launch_map3(const MapGeom &g, int64_t n, int rho, int map, int strict, int32_t *tiles,
+                unsigned long long *slots, hipStream_t s);
+
+constexpr int kEdmTile = 64;     // FP32 difference form: 64 x 64 elements per block
+constexpr int kGramTile = 128;   // Gram form: 128 x 128 elements per block
+constexpr int kGramK = 32;       // Gram K padding
+int launch_edm_diff(const MapGeom &g, const float *X, int64_t n, int64_t d, int64_t ldx, float *D,
+                    unsigned long long *slots, hipStream_t s);
+int launch_gram_prep(const float *X, int64_t n, int64_t d, int64_t ldx, int64_t dpad, uint16_t *hi,
+                     uint16_t *lo, float *norms, bool split, hipStream_t s);
+int launch_edm_gram(const MapGeom &g, const uint16_t *hi, const uint16_t *lo, const float *norms,
+                    int64_t n, int64_t dpad, bool split, float *D, unsigned long long *slots,
+                    hipStream_t s);
+
+constexpr int kTripTile = 32;    // Axilrod-Teller: 32^3 triplets per block
+constexpr int kLjTile = 64;      // Lennard-Jones: 64 x 64 pairs per block
+int launch_triplet(const MapGeom &g, const float *X, int64_t n, int64_t ldx, float nu, bool grad,
+                   double *G64, double *eslots, unsigned long long *sslots, hipStream_t s);
+int launch_lj(const MapGeom &g, const float *X, int64_t n, int64_t ldx, float eps, float sigma,
+              float rc2, double *G64, double *eslots, unsigned long long *sslots, hipStream_t s);
+int launch_energy_finalize(const double *eslots, double *E, hipStream_t s);
+int launch_grad_finalize(const double *G64, int64_t n, const double *gradE, float *out,
+                         hipStream_t s);
+int launch_scale_grad(const float *G, int64_t n, const double *gradE, float *out, hipStream_t s);
+
+}  // namespace smx

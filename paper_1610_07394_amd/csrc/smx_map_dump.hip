@@ -1,0 +1,193 @@
+// Map-dump kernels: every launched block evaluates its map once (block
+// uniform, scalar unit), records its tile, and visits the elements of the tile
+// under the simplex mask, counting them and summing SplitMix64 of their ids.
+// This is the map with an almost empty body: it isolates the cost of the map
+// and of the blocks a map wastes (paper Sec. I and III).
+#include "smx_device.h"
+#include "smx_internal.h"
+
+namespace smx {
+
+constexpr int kMapThreads = 256;
+
+__global__ void fill_u64_kernel(uint64_t *p, size_t count) {
+    const size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < count) p[i] = 0;
+}
+
+int launch_fill_u64(uint64_t *p, size_t count, hipStream_t s) {
+    if (count == 0) return SMX_OK;
+    const unsigned blocks = unsigned((count + 255) / 256);
+    hipLaunchKernelGGL(fill_u64_kernel, dim3(blocks), dim3(256), 0, s, p, count);
+    return check_launch("fill");
+}
+
+__global__ void stats_finalize_kernel(const unsigned long long *slots, uint64_t launched,
+                                      int64_t *out) {
+    __shared__ unsigned long long red[3][kSlots / kWave];
+    const int t = threadIdx.x;  // kSlots threads
+    unsigned long long v[3];
+    for (int c = 0; c < 3; ++c) v[c] = wave_sum(slots[t * kSlotStride + c]);
+    if ((t & (kWave - 1)) == 0)
+        for (int c = 0; c < 3; ++c) red[c][t / kWave] = v[c];
+    __syncthreads();
+    if (t == 0) {
+        for (int c = 0; c < 3; ++c) {
+            unsigned long long r = 0;
+            for (int w = 0; w < kSlots / kWave; ++w) r += red[c][w];
+            out[c] = int64_t(r);
+        }
+        out[3] = int64_t(launched);
+    }
+}
+
+int launch_stats_finalize(const unsigned long long *slots, uint64_t launched, int64_t *d_stats,
+                          hipStream_t s) {
+    prof_begin(K_FINALIZE, s);
+    hipLaunchKernelGGL(stats_finalize_kernel, dim3(1), dim3(kSlots), 0, s, slots, launched,
+                       d_stats);
+    prof_end(K_FINALIZE, s);
+    return check_launch("stats finalize");
+}
+
+// Resolve the tile of this block.  Returns false for a filtered block.  `lin`
+// receives the logical block index used for the dump position.
+template <int MAP>
+__device__ __forceinline__ bool block_tile2(const MapGeom &g, uint64_t &lin, int &X, int &Y) {
+    if (MAP == MAP_BBOX) {
+        X = int(blockIdx.x);
+        Y = int(blockIdx.y);
+        lin = uint64_t(Y) * uint64_t(g.nb) + uint64_t(X);
+        return X <= Y;
+    }
+    lin = launch_index();
+    if (lin >= g.G) return false;
+    const uint32_t id = uint32_t(lin);
+    if (MAP == MAP_LAMBDA) return lambda2(id, g.lg, g.nb, X, Y);
+    linear2(id, X, Y);
+    return true;
+}
+
+template <int MAP>
+__device__ __forceinline__ bool block_tile3(const MapGeom &g, uint64_t &lin, int &X, int &Y, int &Z) {
+    if (MAP == MAP_BBOX) {
+        X = int(blockIdx.x);
+        Y = int(blockIdx.y);
+        Z = int(blockIdx.z);
+        lin = (uint64_t(Z) * uint64_t(g.nb) + uint64_t(Y)) * uint64_t(g.nb) + uint64_t(X);
+        return X <= Y && Y <= Z;
+    }
+    lin = launch_index();
+    if (lin >= g.G) return false;
+    const uint32_t id = uint32_t(lin);
+    if (MAP == MAP_LAMBDA) return lambda3(id, g.lg, g.nb, g.main, X, Y, Z);
+    linear3(id, X, Y, Z);
+    return true;
+}
+
+template <int MAP, bool STRICT>
+__global__ __launch_bounds__(kMapThreads) void map2_kernel(MapGeom g, int64_t n, int rho, int lgrho,
+                                                          int32_t *tiles, unsigned long long *slots) {
+    uint64_t lin;
+    int X = -1, Y = -1;
+    const bool ok = block_tile2<MAP>(g, lin, X, Y);
+    if (MAP != MAP_BBOX && lin >= g.G) return;  // tail of a 2-D launch
+    if (tiles != nullptr && threadIdx.x == 0) {
+        tiles[2 * lin + 0] = ok ? X : -1;
+        tiles[2 * lin + 1] = ok ? Y : -1;
+    }
+    if (!ok || slots == nullptr) return;
+    __shared__ unsigned long long red[2][kMapThreads / kWave];
+    unsigned long long cnt = 0, cs = 0;
+    const int64_t i0 = int64_t(X) * rho, j0 = int64_t(Y) * rho;
+    const int rmask = rho - 1;
+    for (int e = threadIdx.x; e < rho * rho; e += kMapThreads) {
+        const int64_t i = i0 + (e >> lgrho), j = j0 + (e & rmask);
+        const bool v = j < n && (STRICT ? i < j : i <= j);
+        if (v) {
+            ++cnt;
+            cs += mix64(STRICT ? id_pair_lt(i, j) : id_pair_le(i, j, uint64_t(n)));
+        }
+    }
+    const unsigned long long c = block_sum<unsigned long long, kMapThreads>(cnt, red[0]);
+    const unsigned long long h = block_sum<unsigned long long, kMapThreads>(cs, red[1]);
+    if (threadIdx.x == 0) stats_add(slots, lin, c, h);
+}
+
+template <int MAP, bool STRICT>
+__global__ __launch_bounds__(kMapThreads) void map3_kernel(MapGeom g, int64_t n, int rho, int lgrho,
+                                                          int32_t *tiles, unsigned long long *slots) {
+    uint64_t lin;
+    int X = -1, Y = -1, Z = -1;
+    const bool ok = block_tile3<MAP>(g, lin, X, Y, Z);
+    if (MAP != MAP_BBOX && lin >= g.G) return;
+    if (tiles != nullptr && threadIdx.x == 0) {
+        tiles[3 * lin + 0] = ok ? X : -1;
+        tiles[3 * lin + 1] = ok ? Y : -1;
+        tiles[3 * lin + 2] = ok ? Z : -1;
+    }
+    if (!ok || slots == nullptr) return;
+    __shared__ unsigned long long red[2][kMapThreads / kWave];
+    unsigned long long cnt = 0, cs = 0;
+    const int64_t i0 = int64_t(X) * rho, j0 = int64_t(Y) * rho, k0 = int64_t(Z) * rho;
+    const int rmask = rho - 1;
+    for (int e = threadIdx.x; e < rho * rho * rho; e += kMapThreads) {
+        const int64_t i = i0 + (e >> (2 * lgrho)), j = j0 + ((e >> lgrho) & rmask), k = k0 + (e & rmask);
+        const bool v = k < n && (STRICT ? (i < j && j < k) : (i <= j && j <= k));
+        if (v) {
+            ++cnt;
+            cs += mix64(STRICT ? id_trip_lt(i, j, k) : id_trip_le(i, j, k));
+        }
+    }
+    const unsigned long long c = block_sum<unsigned long long, kMapThreads>(cnt, red[0]);
+    const unsigned long long h = block_sum<unsigned long long, kMapThreads>(cs, red[1]);
+    if (threadIdx.x == 0) stats_add(slots, lin, c, h);
+}
+
+template <int MAP>
+static void go_map2(const MapGeom &g, int64_t n, int rho, int lgrho, int strict, int32_t *tiles,
+                    unsigned long long *slots, hipStream_t s) {
+    const dim3 grid = MAP == MAP_BBOX ? dim3(g.nb, g.nb, 1) : grid_for(g.G, kMapThreads);
+    if (strict)
+        hipLaunchKernelGGL((map2_kernel<MAP, true>), grid, dim3(kMapThreads), 0, s, g, n, rho, lgrho,
+                           tiles, slots);
+    else
+        hipLaunchKernelGGL((map2_kernel<MAP, false>), grid, dim3(kMapThreads), 0, s, g, n, rho, lgrho,
+                           tiles, slots);
+}
+
+template <int MAP>
+static void go_map3(const MapGeom &g, int64_t n, int rho, int lgrho, int strict, int32_t *tiles,
+                    unsigned long long *slots, hipStream_t s) {
+    const dim3 grid = MAP == MAP_BBOX ? dim3(g.nb, g.nb, g.nb) : grid_for(g.G, kMapThreads);
+    if (strict)
+        hipLaunchKernelGGL((map3_kernel<MAP, true>), grid, dim3(kMapThreads), 0, s, g, n, rho, lgrho,
+                           tiles, slots);
+    else
+        hipLaunchKernelGGL((map3_kernel<MAP, false>), grid, dim3(kMapThreads), 0, s, g, n, rho, lgrho,
+                           tiles, slots);
+}
+
+int launch_map2(const MapGeom &g, int64_t n, int rho, int map, int strict, int32_t *tiles,
+                unsigned long long *slots, hipStream_t s) {
+    const int lgrho = floor_log2_u32(uint32_t(rho));
+    prof_begin(K_MAP2, s);
+    if (map == MAP_LAMBDA) go_map2<MAP_LAMBDA>(g, n, rho, lgrho, strict, tiles, slots, s);
+    else if (map == MAP_BBOX) go_map2<MAP_BBOX>(g, n, rho, lgrho, strict, tiles, slots, s);
+    else go_map2<MAP_LINEAR>(g, n, rho, lgrho, strict, tiles, slots, s);
+    prof_end(K_MAP2, s);
+    return check_launch("simplex_map2");
+}
+
+int launch_map3(const MapGeom &g, int64_t n, int rho, int map, int strict, int32_t *tiles,
+                unsigned long long *slots, hipStream_t s) {
+    const int lgrho = floor_log2_u32(uint32_t(rho));
+    prof_begin(K_MAP3, s);
+    if (map == MAP_LAMBDA) go_map3<MAP_LAMBDA>(g, n, rho, lgrho, strict, tiles, slots, s);
+    else if (map == MAP_BBOX) go_map3<MAP_BBOX>(g, n, rho, lgrho, strict, tiles, slots, s);
+    else go_map3<MAP_LINEAR>(g, n, rho, lgrho, strict, tiles, slots, s);
+    prof_end(K_MAP3, s);
+    return check_launch("simplex_map3");
+}
+
+}  // namespace smx

@@ -1,0 +1,205 @@
+// Block-space maps from a launched block to a simplex tile.
+//
+// Every function here is block-uniform: it depends only on the block index,
+// so on gfx950 the integer work runs on the scalar unit (s_flbit for clz,
+// s_lshl / s_lshr for powers of two) and costs no vector ALU slots.  The same
+// inline code is compiled for the host so the host-side query can evaluate it.
+//
+// Tile targets: T2 = {X <= Y < nb}, T3 = {X <= Y <= Z < nb}.
+#pragma once
+#include <stdint.h>
+
+#if defined(__HIPCC__)
+#include <hip/hip_runtime.h>
+#define SMX_HD __host__ __device__ __forceinline__
+#else
+#include <cmath>
+#define SMX_HD inline
+#endif
+
+namespace smx {
+
+enum MapKind { MAP_LAMBDA = 0, MAP_BBOX = 1, MAP_LINEAR = 2 };
+
+// floor(log2 v), v >= 1.  The paper's bit-level form (Sec. III-A) counts from
+// the word size W: floor(log2 v) = (W - 1) - clz(v), 2^floor(log2 v) = 1 << that.
+SMX_HD int floor_log2_u32(uint32_t v) { return 31 - __builtin_clz(v); }
+
+SMX_HD int ceil_log2_u64(uint64_t v) {
+    int l = 0;
+    while ((uint64_t(1) << l) < v) ++l;
+    return l;
+}
+
+// Geometry shared by host sizing and device evaluation.
+struct MapGeom {
+    int32_t nb;     // tiles per dimension
+    int32_t lg;     // log2 of nb' = next power of two >= nb (lambda maps)
+    uint32_t main;  // lambda3: blocks of the orthotope Pi3 (before the plane grid)
+    uint32_t map;   // MapKind of the launch
+    uint64_t G;     // logical blocks launched
+};
+
+// ---------------------------------------------------------------- lambda2
+// Sec. III-A.  Parallel space (nb'/2) x (nb'+1), linearised x fastest.  Rows
+// 1..nb'-1: b = 2^floor(log2 w_y), q = floor(w_x / b),
+// lambda(w) = (w_x + q b, w_y + 2 q b), a tile strictly above the diagonal.
+// Rows 0 and nb' carry the diagonal: (w_x, w_x) and (nb'/2 + w_x, nb'/2 + w_x).
+// nb' = 1 is a single block mapped to (0, 0).
+SMX_HD uint64_t lambda2_blocks(int lg) {
+    return lg == 0 ? 1 : (uint64_t(1) << (lg - 1)) * ((uint64_t(1) << lg) + 1);
+}
+
+SMX_HD bool lambda2(uint32_t id, int lg, int nb, int &X, int &Y) {
+    if (lg == 0) {
+        X = 0;
+        Y = 0;
+        return nb > 0;
+    }
+    const int h = lg - 1;
+    const uint32_t wx = id & ((1u << h) - 1u);
+    const uint32_t wy = id >> h;
+    uint32_t x, y;
+    if (wy == 0) {
+        x = wx;
+        y = wx;
+    } else if (wy == (1u << lg)) {
+        x = (1u << h) + wx;
+        y = x;
+    } else {
+        const int L = floor_log2_u32(wy);
+        const uint32_t q = wx >> L;
+        x = wx + (q << L);
+        y = wy + (q << (L + 1));
+    }
+    X = int(x);
+    Y = int(y);
+    return y < uint32_t(nb);  // x <= y
+}
+
+// ---------------------------------------------------------------- lambda3
+// Sec. III-C, two recursion branches.  Pi3 = (nb'/2) x (nb'/2) x (nb'/2 + nb'/4),
+// linearised x fastest.  Target of Pi3: {X <= Y < Z}.  The first nb'/2
+// z-slices are the main cube, level b = nb'/2, offset o = 0, (u, v, w) = w.
+// The other slices are a slab reusing lambda2's level of w_y:
+// w = w_z - nb'/2, b = 2^floor(log2 w_y), q = floor(w_x / b), u = w_x - q b,
+// v = w_y - b, o = 2 q b; blocks with w_y = 0 or w >= b are filtered.  Each b^3
+// block-cube folds across its diagonal plane onto the cross cube
+// {o <= X < o+b <= Z < o+2b} of the tetrahedron:
+//   v <  w : (o + u, o + b + v, o + b + w)
+//   v >= w : (o + w, o + v,     o + b + u)
+// Blocks past Pi3 form a lambda2 grid over nb whose tile (X, Y) becomes the
+// plane tile (X, Y, Y).
+SMX_HD uint32_t lambda3_main_blocks(int lg) {
+    if (lg == 0) return 0;
+    const uint32_t half = 1u << (lg - 1);
+    return half * half * (half + (half >> 1));
+}
+
+SMX_HD bool lambda3(uint32_t id, int lg, int nb, uint32_t main, int &X, int &Y, int &Z) {
+    if (id < main) {
+        const int h = lg - 1;
+        const uint32_t half = 1u << h;
+        const uint32_t wx = id & (half - 1u);
+        const uint32_t wy = (id >> h) & (half - 1u);
+        const uint32_t wz = id >> (2 * h);
+        uint32_t u, v, w, b, o;
+        if (wz < half) {
+            u = wx;
+            v = wy;
+            w = wz;
+            b = half;
+            o = 0;
+        } else {
+            w = wz - half;
+            if (wy == 0) return false;
+            const int L = floor_log2_u32(wy);
+            b = 1u << L;
+            if (w >= b) return false;
+            const uint32_t q = wx >> L;
+            u = wx - (q << L);
+            v = wy - b;
+            o = q << (L + 1);
+        }
+        uint32_t x, y, z;
+        if (v < w) {
+            x = o + u;
+            y = o + b + v;
+            z = o + b + w;
+        } else {
+            x = o + w;
+            y = o + v;
+            z = o + b + u;
+        }
+        X = int(x);
+        Y = int(y);
+        Z = int(z);
+        return z < uint32_t(nb);
+    }
+    int x2, y2;
+    if (!lambda2(id - main, lg, nb, x2, y2)) return false;
+    X = x2;
+    Y = y2;
+    Z = y2;
+    return true;
+}
+
+// ---------------------------------------------------------------- linear
+// Linear enumeration (Sec. I): block k is the k-th tile of T2 listed by Y
+// then X, or of T3 listed by Z, Y, X.  The root of the quadratic (cubic) is
+// taken in FP32 and then corrected with exact integer comparisons, so the
+// result is exact for every k although FP32 roots are not once k > 2^24.
+SMX_HD uint64_t tri_u64(uint64_t y) { return y * (y + 1) / 2; }
+SMX_HD uint64_t tet_u64(uint64_t z) { return z * (z + 1) * (z + 2) / 6; }
+
+SMX_HD uint32_t tri_root(uint64_t k) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    const float f = __builtin_sqrtf(8.0f * float(k) + 1.0f);
+#else
+    const float f = std::sqrt(8.0f * float(k) + 1.0f);
+#endif
+    float g = (f - 1.0f) * 0.5f;
+    uint64_t y = g > 0.0f ? uint64_t(g) : 0;
+    while (y > 0 && tri_u64(y) > k) --y;
+    while (tri_u64(y + 1) <= k) ++y;
+    return uint32_t(y);
+}
+
+SMX_HD uint32_t tet_root(uint64_t k) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    const float f = cbrtf(6.0f * float(k));
+#else
+    const float f = std::cbrt(6.0f * float(k));
+#endif
+    uint64_t z = f > 1.0f ? uint64_t(f) - 1 : 0;
+    while (z > 0 && tet_u64(z) > k) --z;
+    while (tet_u64(z + 1) <= k) ++z;
+    return uint32_t(z);
+}
+
+SMX_HD void linear2(uint32_t k, int &X, int &Y) {
+    const uint32_t y = tri_root(k);
+    Y = int(y);
+    X = int(uint64_t(k) - tri_u64(y));
+}
+
+SMX_HD void linear3(uint32_t k, int &X, int &Y, int &Z) {
+    const uint32_t z = tet_root(k);
+    const uint64_t r = uint64_t(k) - tet_u64(z);
+    const uint32_t y = tri_root(r);
+    Z = int(z);
+    Y = int(y);
+    X = int(r - tri_u64(y));
+}
+
+// ---------------------------------------------------------------- XCD order
+// Workgroups are dispatched round-robin over the 8 XCDs of the chip, each with
+// its own L2.  Renumbering dispatch index b so that XCD (b mod 8) receives one
+// contiguous range of logical blocks keeps neighbouring tiles, which share
+// input rows, in one L2.  A bijection on [0, G).
+SMX_HD uint32_t xcd_remap(uint32_t b, uint32_t G) {
+    const uint32_t chunk = G >> 3, rem = G & 7u, x = b & 7u, s = b >> 3;
+    return x * chunk + (x < rem ? x : rem) + s;
+}
+
+}  // namespace smx

@@ -1,0 +1,158 @@
+"""CPU tests of the C-ABI library: it loads, exports every symbol the header
+declares, validates arguments on the host before any HIP call, and its inline
+map code (evaluated on the host) equals the oracle's maps.  No device work."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_1610_07394_amd as smx
+from oracle import maps as omaps
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "smx.h")
+
+
+def _declared():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(smx_[a-z0-9_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    names = _declared()
+    assert len(names) >= 14
+    L = ctypes.CDLL(smx.LIB_PATH)
+    missing = [n for n in names if not hasattr(L, n)]
+    assert not missing, missing
+
+
+def test_version_and_volume():
+    assert "gfx950" in smx.version()
+    for n in (0, 1, 2, 3, 10, 1024, 65536):
+        assert smx.volume(2, n) == n * (n + 1) // 2
+        assert smx.volume(2, n, strict=True) == n * (n - 1) // 2 if n > 0 else smx.volume(2, n, True) == 0
+        assert smx.volume(3, n) == n * (n + 1) * (n + 2) // 6
+        assert smx.volume(3, n, strict=True) == max(0, n * (n - 1) * (n - 2) // 6)
+    assert smx.volume(4, 10) == -1
+    assert smx.volume(2, -1) == -1
+
+
+@pytest.mark.parametrize("m,n,rho", [(2, 1024, 16), (2, 65536, 64), (2, 1000, 16), (3, 2048, 32),
+                                     (3, 8192, 32), (3, 100, 8), (2, 1, 16), (3, 5, 1)])
+@pytest.mark.parametrize("kind", ["lambda", "bbox", "linear"])
+def test_parallel_blocks_match_oracle(m, n, rho, kind):
+    nb = (n + rho - 1) // rho
+    if m == 3 and kind == "bbox" and nb > 64:
+        expect = nb ** 3
+    else:
+        expect = omaps.tiles(m, nb, kind).shape[0]
+    assert smx.parallel_blocks(m, n, rho, kind) == expect
+
+
+@pytest.mark.parametrize("nb", [1, 2, 3, 4, 7, 8, 16, 33, 64, 100, 512, 1024, 4096])
+@pytest.mark.parametrize("kind", ["lambda", "bbox", "linear"])
+def test_host_map2_equals_oracle(nb, kind):
+    if kind == "bbox" and nb > 1024:
+        pytest.skip("bbox dump of nb^2 blocks checked at smaller nb")
+    got = smx.map_tiles_host(2, nb, 1, kind)
+    want = omaps.tiles(2, nb, kind)
+    np.testing.assert_array_equal(got, want)
+
+
+@pytest.mark.parametrize("nb", [1, 2, 3, 4, 5, 8, 16, 31, 64, 128, 256])
+@pytest.mark.parametrize("kind", ["lambda", "bbox", "linear"])
+def test_host_map3_equals_oracle(nb, kind):
+    if kind == "bbox" and nb > 64:
+        pytest.skip("bbox dump of nb^3 blocks checked at smaller nb")
+    got = smx.map_tiles_host(3, nb, 1, kind)
+    want = omaps.tiles(3, nb, kind)
+    np.testing.assert_array_equal(got, want)
+
+
+def test_linear_map_exact_where_fp32_roots_are_not():
+    """Block indices near 2^31 map exactly although a plain FP32 root is wrong there."""
+    nb = 65535  # linear grid of nb (nb + 1) / 2 = 2,147,450,880 blocks
+    # k = T(y) - 1 and T(y) around the largest rows
+    ys = np.arange(nb - 3000, nb + 1, dtype=np.int64)
+    ks = np.concatenate([ys * (ys + 1) // 2 - 1, ys[:-1] * (ys[:-1] + 1) // 2])
+    ks = ks[(ks >= 0) & (ks < nb * (nb + 1) // 2)]
+    f32 = np.floor((np.sqrt(8 * ks.astype(np.float32) + np.float32(1)) - np.float32(1)) / np.float32(2))
+    y_true = np.searchsorted(np.arange(nb + 2, dtype=np.int64) * np.arange(1, nb + 3, dtype=np.int64) // 2,
+                             ks, side="right") - 1
+    assert (f32.astype(np.int64) != y_true).any()  # FP32 alone fails in this range
+    for k, yt in zip(ks[::97], y_true[::97]):
+        t = smx.map_tiles_host(2, nb, 1, "linear", first=int(k), count=1)[0]
+        assert t[1] == yt and t[0] == k - yt * (yt + 1) // 2
+
+
+def _call(fn, *a):
+    return fn(*a)
+
+
+def test_validation_errors_before_any_device_work():
+    L = smx.lib()
+    null = None
+    st = ctypes.c_void_p(0)
+    # bad map / rho / n on the map dumps
+    assert L.smx_simplex_map2(16, 16, 7, 0, null, null, null, 0, null) == 1
+    assert L.smx_simplex_map2(16, 3, 0, 0, null, null, null, 0, null) == 1
+    assert L.smx_simplex_map2(-1, 16, 0, 0, null, null, null, 0, null) == 1
+    assert L.smx_simplex_map3(16, 128, 0, 0, null, null, null, 0, null) == 1
+    assert b"rho" in L.smx_last_error()
+    # stats without a workspace
+    assert L.smx_simplex_map2(16, 16, 0, 0, null, ctypes.c_void_p(8), null, 0, null) == 1
+    # n = 0 is a no-op
+    assert L.smx_simplex_map2(0, 16, 0, 0, null, null, null, 0, null) == 0
+    # EDM argument checks
+    assert L.smx_edm_packed(null, 10, 0, 3, 0, 0, null, null, 0, null, null) == 1
+    assert L.smx_edm_packed(null, 10, 3, 2, 0, 0, null, null, 0, null, null) == 1
+    assert L.smx_edm_packed(null, 10, 3, 3, 5, 0, null, null, 0, null, null) == 1
+    assert L.smx_edm_packed(null, 10, 3, 3, 0, 9, null, null, 0, null, null) == 1
+    assert L.smx_edm_packed(null, 10, 3, 3, 0, 0, null, null, 0, null, null) == 1  # NULL X / D
+    assert L.smx_edm_packed(ctypes.c_void_p(256), 10, 3, 3, 0, 1, ctypes.c_void_p(256), null, 0, null,
+                            null) == 1  # Gram without workspace
+    assert b"workspace" in L.smx_last_error()
+    assert L.smx_edm_packed(null, 0, 3, 3, 0, 0, null, null, 0, null, null) == 0
+    assert L.smx_edm_packed(null, 1 << 31, 3, 3, 0, 0, null, null, 0, null, null) == 2
+    # triplet checks
+    pot = smx.Pot()._c()
+    assert L.smx_triplet_energy(null, 10, 2, ctypes.byref(pot), 0, null, null, 0, null, null) == 1
+    assert L.smx_triplet_energy(null, 10, 3, None, 0, null, null, 0, null, null) == 1
+    assert L.smx_triplet_energy(null, 10, 3, ctypes.byref(pot), 0, null, null, 0, null, null) == 1
+    bad = smx.Pot(lj=True, rc=-1.0)._c()
+    assert L.smx_triplet_energy(ctypes.c_void_p(256), 10, 3, ctypes.byref(bad), 0, ctypes.c_void_p(256),
+                                ctypes.c_void_p(256), 1 << 20, null, null) == 1
+    assert L.smx_triplet_energy_backward(ctypes.c_void_p(256), 10, 3, ctypes.byref(pot), 0, null,
+                                         ctypes.c_void_p(256), ctypes.c_void_p(256), 1 << 20, null) == 1
+    assert L.smx_scale_grad(null, -1, null, null, null) == 1
+    assert L.smx_scale_grad(null, 0, null, null, null) == 0
+    ms, cnt = ctypes.c_double(), ctypes.c_int64()
+    assert L.smx_profile_read(99, ctypes.byref(ms), ctypes.byref(cnt)) == 1
+
+
+def test_grid_overflow_is_reported():
+    # lambda3 past 2^31 blocks, bounding box past the grid dimension limit
+    assert smx.lib().smx_parallel_blocks(3, 1 << 22, 1, 0) == -1
+    assert smx.lib().smx_parallel_blocks(2, 1 << 17, 1, 1) == -1
+
+
+def test_workspace_sizes():
+    assert smx.workspace_bytes(0, 100) == 256 * 128
+    w_fp32 = smx.workspace_bytes(1, 1000, 64, 0)
+    w_bf16 = smx.workspace_bytes(1, 1000, 64, 1)
+    w_split = smx.workspace_bytes(1, 1000, 64, 2)
+    assert w_fp32 < w_bf16 < w_split
+    assert w_split - w_bf16 >= 1000 * 64 * 2
+    assert smx.workspace_bytes(2, 8192) >= 8192 * 3 * 8
+
+
+def test_binding_rejects_host_tensors():
+    import torch
+    X = torch.zeros((4, 3), dtype=torch.float32)
+    with pytest.raises(ValueError):
+        smx.edm_packed(X)
+    with pytest.raises(ValueError):
+        smx.triplet_energy(X)

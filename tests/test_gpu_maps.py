@@ -1,0 +1,102 @@
+"""GPU parity of the map kernels: tile dumps bit-exact against the oracle's
+maps, element counts and checksums exact against the oracle's simplex
+checksums, for the lambda, bounding-box and linear maps."""
+import json
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_1610_07394_amd as smx
+from oracle import maps as omaps
+
+pytestmark = pytest.mark.gpu
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden", "expected.json")
+KINDS = ["lambda", "bbox", "linear"]
+
+
+def _gold():
+    with open(GOLD) as f:
+        return json.load(f)
+
+
+def _u64(v):
+    return int(v) % (1 << 64)
+
+
+def _run(m, n, rho, kind, strict, tiles=True):
+    print(f"map{m} n={n} rho={rho} {kind} strict={strict}", flush=True)
+    fn = smx.simplex_map2 if m == 2 else smx.simplex_map3
+    t, s = fn(n, rho, kind, strict=strict, tiles=tiles)
+    torch.cuda.synchronize()
+    return (None if t is None else t.cpu().numpy()), s.cpu().numpy()
+
+
+def _check_stats(s, m, n, rho, kind, strict):
+    nb = -(-n // rho)
+    V = oracle.simplex_volume(m, n, strict)
+    assert int(s[0]) == V
+    assert _u64(s[1]) == oracle.checksum_range(V)
+    ntiles = nb * (nb + 1) // 2 if m == 2 else nb * (nb + 1) * (nb + 2) // 6
+    assert int(s[2]) == ntiles
+    assert int(s[3]) == smx.parallel_blocks(m, n, rho, kind)
+
+
+CASES2 = [(1024, 16), (1000, 16), (1, 16), (2, 1), (5, 1), (64, 1), (300, 64), (65, 8), (4096, 256),
+          (3000, 1024)]
+
+
+@pytest.mark.parametrize("n,rho", CASES2)
+@pytest.mark.parametrize("kind", KINDS)
+@pytest.mark.parametrize("strict", [False, True])
+def test_map2_dump_and_counts(n, rho, kind, strict):
+    t, s = _run(2, n, rho, kind, strict)
+    nb = -(-n // rho)
+    np.testing.assert_array_equal(t, omaps.tiles(2, nb, kind))
+    _check_stats(s, 2, n, rho, kind, strict)
+
+
+CASES3 = [(64, 8), (100, 8), (33, 4), (1, 8), (8, 1), (17, 1), (256, 16), (200, 32), (1024, 64)]
+
+
+@pytest.mark.parametrize("n,rho", CASES3)
+@pytest.mark.parametrize("kind", KINDS)
+@pytest.mark.parametrize("strict", [False, True])
+def test_map3_dump_and_counts(n, rho, kind, strict):
+    t, s = _run(3, n, rho, kind, strict)
+    nb = -(-n // rho)
+    np.testing.assert_array_equal(t, omaps.tiles(3, nb, kind))
+    _check_stats(s, 3, n, rho, kind, strict)
+
+
+@pytest.mark.parametrize("kind", KINDS)
+def test_map2_full_size_counts(kind):
+    """n = 65536 at the paper-like granularity rho = 16 (8.4M lambda blocks)."""
+    _, s = _run(2, 65536, 16, kind, False, tiles=False)
+    g = _gold()["checksums"]["pairs_le_65536"]
+    assert int(s[0]) == g["volume"] and _u64(s[1]) == int(g["checksum"])
+    assert int(s[2]) == 4096 * 4097 // 2
+
+
+@pytest.mark.parametrize("kind", KINDS)
+@pytest.mark.parametrize("strict", [False, True])
+def test_map3_full_size_counts(kind, strict):
+    """n = 8192 triplets with 32^3 tiles: 9.2e10 elements counted exactly."""
+    _, s = _run(3, 8192, 32, kind, strict, tiles=False)
+    g = _gold()["checksums"]["triplets_lt_8192" if strict else "triplets_le_8192"]
+    assert int(s[0]) == g["volume"] and _u64(s[1]) == int(g["checksum"])
+    assert int(s[2]) == 256 * 257 * 258 // 6
+
+
+def test_lambda_block_counts_match_paper_ratios():
+    """|Pi2| = |T2| exactly; |Pi3| / |T3 minus plane| = 9/8 + O(1/nb) (12.5% extra)."""
+    for n, rho in ((65536, 16), (8192, 32)):
+        nb = n // rho
+        assert smx.parallel_blocks(2, n, rho, "lambda") == nb * (nb + 1) // 2
+    nb = 256
+    main = smx.parallel_blocks(3, 8192, 32, "lambda") - nb * (nb + 1) // 2
+    assert main == 3 * nb ** 3 // 16
+    assert abs(main / ((nb ** 3 - nb) / 6) - 9 / 8) < 1e-4

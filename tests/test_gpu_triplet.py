@@ -1,0 +1,218 @@
+"""GPU parity of the triplet energy and gradient against the FP64 oracle.
+
+Error metrics (relative error <= 1e-5 for FP32 energies and forces):
+* energy: |E^ - E| / |E|;
+* gradient / forces: max_i |G^_i - G_i|_2 / max_i |G_i|_2 (a per-particle
+  relative error is undefined where a force nearly cancels).
+The gradient is also checked against fourth-order central differences of the
+oracle's FP64 energy at n = 64.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_1610_07394_amd as smx
+import synth
+
+pytestmark = pytest.mark.gpu
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden", "expected.json")
+KINDS = ["lambda", "bbox", "linear"]
+AT = smx.Pot(nu=1.0, at=True, lj=False)
+ATLJ = smx.Pot(nu=1.0, at=True, lj=True, eps=1.0, sigma=1.0, rc=3.0)
+
+
+def _pts(n, seed):
+    """RSA points at the density of the n = 8192, side 20 workload."""
+    side = max(1.5, 20.0 * (max(n, 1) / 8192) ** (1 / 3))
+    return synth.rsa(n, seed=seed, side=side, dmin=0.8) if n > 0 else np.zeros((0, 3), np.float32)
+
+
+def _fmetric(G, ref):
+    den = np.linalg.norm(ref, axis=1).max()
+    return float(np.linalg.norm(G - ref, axis=1).max() / den)
+
+
+def _gpu(X):
+    return torch.from_numpy(np.ascontiguousarray(X)).cuda()
+
+
+@pytest.mark.parametrize("n", [3, 4, 5, 31, 32, 33, 64, 65, 100, 257])
+@pytest.mark.parametrize("kind", KINDS)
+def test_at_energy_grad_vs_oracle(n, kind):
+    print(f"at n={n} {kind}", flush=True)
+    X = _pts(n, seed=n)
+    Xt = _gpu(X)
+    E, s = smx.triplet_energy(Xt, AT, kind, stats=True)
+    E2, G = smx.triplet_energy_grad(Xt, AT, kind)
+    torch.cuda.synchronize()
+    e_ref = oracle.at_energy(X)
+    assert abs(E[0].item() - e_ref) <= 1e-5 * abs(e_ref)
+    assert E[1].item() == E[0].item() and E[2].item() == 0.0
+    assert abs(E2[0].item() - e_ref) <= 1e-5 * abs(e_ref)
+    g_ref = oracle.at_grad(X)
+    err = _fmetric(G.cpu().numpy().astype(np.float64), g_ref)
+    print(f"  energy rel {abs(E[0].item() - e_ref) / abs(e_ref):.2e} grad {err:.2e}")
+    assert err <= 1e-5
+    s = s.cpu().numpy()
+    V = math.comb(n, 3)
+    assert int(s[0]) == V and int(s[1]) % (1 << 64) == oracle.checksum_range(V)
+
+
+@pytest.mark.parametrize("kind", KINDS)
+def test_lj_single_pair(kind):
+    """One pair: the LJ force is the difference of the r^-13 and r^-7 terms and
+    vanishes at r = 2^(1/6) sigma, so its FP32 error is bounded relative to the
+    term scale 48 eps sigma^12 / r^13 + 24 eps sigma^6 / r^7, not to the net force
+    (near the minimum the 2^-24 rounding of the pair vector alone moves the force
+    by ~ 57 eps/sigma^2 * r * 2^-23)."""
+    for r in (0.85, 1.0, 2.0 ** (1 / 6), 1.3, 2.5):
+        X = np.array([[1.0, 2.0, 3.0], [1.0 + r * 0.6, 2.0 + r * 0.8, 3.0]], np.float32)
+        Xt = _gpu(X)
+        E = smx.triplet_energy(Xt, ATLJ, kind).cpu().numpy()
+        _, G = smx.triplet_energy_grad(Xt, ATLJ, kind)
+        e_ref = oracle.lj_energy(X)
+        rr = float(np.linalg.norm(X[1].astype(np.float64) - X[0]))
+        assert E[1] == 0.0
+        assert abs(E[2] - e_ref) <= 1e-5 * 4 * (rr ** -12 + rr ** -6)
+        scale = 48 * rr ** -13 + 24 * rr ** -7
+        err = np.abs(G.cpu().numpy().astype(np.float64) - oracle.lj_grad(X)).max()
+        assert err <= 1e-5 * scale
+
+
+@pytest.mark.parametrize("n", [3, 64, 65, 130, 500])
+@pytest.mark.parametrize("kind", KINDS)
+def test_at_plus_lj_vs_oracle(n, kind):
+    print(f"at+lj n={n} {kind}", flush=True)
+    X = _pts(n, seed=100 + n)
+    Xt = _gpu(X)
+    E, s = smx.triplet_energy(Xt, ATLJ, kind, stats=True)
+    _, G = smx.triplet_energy_grad(Xt, ATLJ, kind)
+    torch.cuda.synchronize()
+    e_at, e_lj = oracle.at_energy(X), oracle.lj_energy(X)
+    E = E.cpu().numpy()
+    assert abs(E[1] - e_at) <= 1e-5 * abs(e_at)
+    assert abs(E[2] - e_lj) <= 1e-5 * abs(e_lj)
+    assert abs(E[0] - (e_at + e_lj)) <= 1e-5 * (abs(e_at) + abs(e_lj))
+    g_ref = oracle.at_grad(X) + oracle.lj_grad(X)
+    assert _fmetric(G.cpu().numpy().astype(np.float64), g_ref) <= 1e-5
+    s = s.cpu().numpy()
+    assert int(s[4]) == math.comb(n, 2) and int(s[5]) % (1 << 64) == oracle.checksum_range(math.comb(n, 2))
+
+
+@pytest.mark.parametrize("n", [0, 1, 2])
+def test_degenerate_sizes(n):
+    X = _pts(n, seed=1) if n > 0 else np.zeros((0, 3), np.float32)
+    Xt = torch.from_numpy(X).cuda() if n > 0 else torch.zeros((0, 3), dtype=torch.float32, device="cuda")
+    E = smx.triplet_energy(Xt, ATLJ).cpu().numpy()
+    assert E[1] == 0.0
+    if n < 2:
+        assert E[0] == 0.0
+    _, G = smx.triplet_energy_grad(Xt, AT)
+    assert G.shape == (n, 3) and (G.cpu().numpy() == 0).all()
+
+
+def test_ldx4_input():
+    X = _pts(77, seed=3)
+    X4 = np.concatenate([X, np.full((77, 1), 123.0, np.float32)], axis=1)
+    E3 = smx.triplet_energy(_gpu(X), AT)[0].item()
+    E4 = smx.triplet_energy(_gpu(X4), AT)[0].item()
+    assert abs(E4 - E3) <= 1e-12 * abs(E3)
+
+
+def test_gradient_finite_differences_n64():
+    """GPU gradient against 4th-order central differences of the oracle's FP64
+    energy (h = 2^-10, exactly representable on these FP32 coordinates)."""
+    X = _pts(64, seed=64)
+    _, G = smx.triplet_energy_grad(_gpu(X), AT)
+    G = G.cpu().numpy().astype(np.float64)
+    h = 2.0 ** -10
+    fd = np.zeros_like(G)
+    for i in range(64):
+        for c in range(3):
+            vals = []
+            for k in (2, 1, -1, -2):
+                Y = X.copy()
+                Y[i, c] += np.float32(k * h)
+                assert float(Y[i, c]) - float(X[i, c]) == k * h
+                vals.append(oracle.at_energy(Y))
+            fd[i, c] = (-vals[0] + 8 * vals[1] - 8 * vals[2] + vals[3]) / (12 * h)
+    err = _fmetric(G, fd)
+    print(f"  FD error {err:.2e}")
+    assert err <= 1e-5
+
+
+@pytest.mark.parametrize("fused", [True, False])
+def test_autograd_function(fused):
+    X = _pts(100, seed=5)
+    Xt = _gpu(X).requires_grad_(True)
+    E = smx.TripletEnergy.apply(Xt, ATLJ, "lambda", fused)
+    assert E.dtype == torch.float64 and E.dim() == 0
+    (g,) = torch.autograd.grad(E * 2.5, Xt)
+    ref = 2.5 * (oracle.at_grad(X) + oracle.lj_grad(X))
+    assert _fmetric(g.cpu().numpy().astype(np.float64), ref) <= 1e-5
+    forces = -g / 2.5
+    assert np.allclose(forces.sum(0).cpu().numpy(), 0.0, atol=1e-3 * np.abs(ref).max())
+
+
+def test_backward_entry_point_scales():
+    X = _pts(90, seed=6)
+    Xt = _gpu(X)
+    gE = torch.tensor(-1.75, dtype=torch.float64, device="cuda")
+    dX = smx.triplet_energy_backward(Xt, gE, ATLJ, "lambda").cpu().numpy().astype(np.float64)
+    ref = -1.75 * (oracle.at_grad(X) + oracle.lj_grad(X))
+    assert _fmetric(dX, ref) <= 1e-5
+
+
+def test_at_n2048_full_gradient():
+    """The n = 2048 workload: energy and the full gradient against the oracle."""
+    X = synth.workload_input("at_n2048")
+    Xt = _gpu(X)
+    for kind in KINDS:
+        E, G = smx.triplet_energy_grad(Xt, AT, kind)
+        torch.cuda.synchronize()
+        if kind == "lambda":
+            e_ref = oracle.at_energy(X)
+            g_ref = oracle.at_grad(X)
+        rel = abs(E[0].item() - e_ref) / abs(e_ref)
+        err = _fmetric(G.cpu().numpy().astype(np.float64), g_ref)
+        print(f"  {kind}: energy rel {rel:.2e}, grad {err:.2e}", flush=True)
+        assert rel <= 1e-5 and err <= 1e-5
+    _, s = smx.triplet_energy(Xt, AT, "lambda", stats=True)
+    s = s.cpu().numpy()
+    g = json.load(open(GOLD))["checksums"]["triplets_lt_2048"]
+    assert int(s[0]) == g["volume"] and int(s[1]) % (1 << 64) == int(g["checksum"])
+
+
+def test_at_lj_n8192_full_size():
+    """The n = 8192 workload (9.2e10 triplets + 3.4e7 pairs): energies and
+    sampled gradient rows against oracle values, all maps, exact counts."""
+    gold = json.load(open(GOLD))
+    g = gold["at_lj_n8192"]
+    X = synth.workload_input("at_lj_n8192")
+    Xt = _gpu(X)
+    rows = np.array(g["grad_rows"])
+    ref_rows = np.array(g["at_grad_rows"]) + np.array(g["lj_grad_rows"])
+    for kind in KINDS:
+        print(f"  n=8192 {kind}", flush=True)
+        E, G = smx.triplet_energy_grad(Xt, ATLJ, kind)
+        torch.cuda.synchronize()
+        E = E.cpu().numpy()
+        assert abs(E[1] - g["at_energy"]) <= 1e-5 * abs(g["at_energy"])
+        assert abs(E[2] - g["lj_energy"]) <= 1e-5 * abs(g["lj_energy"])
+        Gr = G.cpu().numpy().astype(np.float64)[rows]
+        err = float(np.linalg.norm(Gr - ref_rows, axis=1).max() / np.linalg.norm(G.cpu().numpy(), axis=1).max())
+        print(f"  {kind}: E_at rel {abs(E[1] - g['at_energy']) / abs(g['at_energy']):.2e} "
+              f"rows err {err:.2e}", flush=True)
+        assert err <= 1e-5
+    _, s = smx.triplet_energy(Xt, ATLJ, "lambda", stats=True)
+    s = s.cpu().numpy()
+    c = gold["checksums"]["triplets_lt_8192"]
+    assert int(s[0]) == c["volume"] and int(s[1]) % (1 << 64) == int(c["checksum"])
+    c2 = gold["checksums"]["pairs_lt_8192"]
+    assert int(s[4]) == c2["volume"] and int(s[5]) % (1 << 64) == int(c2["checksum"])
