@@ -47,6 +47,9 @@ def parse():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-compare", action="store_true")
     p.add_argument("--only", default="", help="comma list of edm,gram,at (default all)")
+    p.add_argument("--calibrate-copy", action="store_true",
+                   help="first run one 1 GiB device-to-device copy (known traffic) to scale "
+                        "rocprofv3 FETCH_SIZE / WRITE_SIZE readings")
     return p.parse_args()
 
 
@@ -100,6 +103,13 @@ def main():
     }
     total_elems = sum(elements[p] for p in only)
 
+    if args.calibrate_copy:
+        src = torch.empty(1 << 28, dtype=torch.float32, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)  # reads and writes exactly 1 GiB
+        torch.cuda.synchronize()
+        del src, dst
     log("warmup")
     for _ in range(args.warmup):
         step()
@@ -246,7 +256,7 @@ def cpu_baseline(only, elements, total_elems):
     samples = []
     if "edm" in only:
         X = synth.workload_input("edm_n65536_d64")
-        r = 256
+        r = 16384
         t0 = time.perf_counter()
         oracle.edm_rows(X, 0, r)
         dt = time.perf_counter() - t0
@@ -255,7 +265,7 @@ def cpu_baseline(only, elements, total_elems):
         samples.append(f"EDM d=64 rows 0..{r} ({e} pairs, {dt:.2f}s)")
     if "gram" in only:
         X = synth.workload_input("gram_n32768_d512")
-        r = 64
+        r = 4096
         t0 = time.perf_counter()
         oracle.edm_rows(X, 0, r)
         dt = time.perf_counter() - t0
@@ -264,12 +274,12 @@ def cpu_baseline(only, elements, total_elems):
         samples.append(f"EDM d=512 rows 0..{r} ({e} pairs, {dt:.2f}s)")
     if "at" in only:
         X = synth.workload_input("at_lj_n8192")
-        i1 = 24
+        i1 = 240
         t0 = time.perf_counter()
         oracle.at_energy(X, 1.0, 0, i1)
         dt_e = time.perf_counter() - t0
         tri_e = sum(math.comb(N_AT - 1 - i, 2) for i in range(i1))
-        rows = [0, 1, 2, 3]
+        rows = list(range(0, 8192, 256))
         t0 = time.perf_counter()
         oracle.at_grad_rows(X, rows, 1.0)
         dt_g = time.perf_counter() - t0

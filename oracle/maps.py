@@ -216,15 +216,72 @@ def linear3_tiles(nb: int) -> np.ndarray:
     return np.stack([x, y, z], axis=1)
 
 
-MAPS = {"lambda": 0, "bbox": 1, "linear": 2}
+# --------------------------------------------------------------------------
+# "Approach n from below" (Sec. III-A, second option): cover nb with
+# power-of-two orthotopes n_1 = 2^floor(log2 nb), n_i = 2^floor(log2(nb -
+# sum_{k<i} n_k)) (the binary digits of nb, largest first) plus simpler maps for
+# what they leave.  Segment i = [o_i, o_i + m_i).  Reading written out here:
+#   2-simplex, per segment in order: the lambda2 grid of m_i on the segment's
+#     diagonal triangle, then (if tiles remain above it) the rectangle
+#     [o_i, o_i + m_i) x [o_i + m_i, nb) under the identity, x fastest;
+#   3-simplex, per segment in order: the lambda3 grid of m_i (its tetrahedron),
+#     then the prism {x <= y in segment i, z above it} = lambda2(m_i) x identity
+#     (lambda2 index fastest), then the prism {x in segment i, y <= z above it}
+#     = identity x (2-simplex map from below of the rest), x fastest.
+# Every block of the 2-simplex cover maps to a tile (zero filtered blocks).
+def segments(nb: int) -> list[tuple[int, int]]:
+    out, o, rem = [], 0, nb
+    while rem > 0:
+        m = 1 << (rem.bit_length() - 1)
+        out.append((o, m))
+        o += m
+        rem -= m
+    return out
+
+
+def below2_tiles(nb: int) -> np.ndarray:
+    parts = []
+    for o, m in segments(nb):
+        tri = lambda2_tiles(m) + o
+        parts.append(tri)
+        r = nb - o - m
+        if r > 0:
+            y, x = np.divmod(np.arange(m * r, dtype=np.int64), m)
+            parts.append(np.stack([o + x, o + m + y], axis=1))
+    return np.concatenate(parts, axis=0) if parts else np.zeros((0, 2), np.int64)
+
+
+def below3_tiles(nb: int) -> np.ndarray:
+    parts = []
+    for o, m in segments(nb):
+        tet = lambda3_tiles(m)
+        ok = tet[:, 0] >= 0
+        tet[ok] += o
+        parts.append(tet)
+        r = nb - o - m
+        if r > 0:
+            t2 = lambda2_tiles(m)  # m a power of two: no filtered rows
+            z = np.repeat(np.arange(r, dtype=np.int64), t2.shape[0])
+            pa = np.concatenate([np.tile(t2 + o, (r, 1)), (o + m + z)[:, None]], axis=1)
+            parts.append(pa)
+            b2 = below2_tiles(r) + (o + m)
+            x = np.tile(np.arange(m, dtype=np.int64), b2.shape[0])
+            pb = np.concatenate([(o + x)[:, None], np.repeat(b2, m, axis=0)], axis=1)
+            parts.append(pb)
+    return np.concatenate(parts, axis=0) if parts else np.zeros((0, 3), np.int64)
+
+
+MAPS = {"lambda": 0, "bbox": 1, "linear": 2, "lambda_below": 3}
 
 
 def tiles(m: int, nb: int, kind: str) -> np.ndarray:
     """Tile dump of map ``kind`` ('lambda', 'bbox', 'linear') for T2 (m=2) or T3 (m=3)."""
     if m == 2:
-        return {"lambda": lambda2_tiles, "bbox": bbox2_tiles, "linear": linear2_tiles}[kind](nb)
+        return {"lambda": lambda2_tiles, "bbox": bbox2_tiles, "linear": linear2_tiles,
+                "lambda_below": below2_tiles}[kind](nb)
     if m == 3:
-        return {"lambda": lambda3_tiles, "bbox": bbox3_tiles, "linear": linear3_tiles}[kind](nb)
+        return {"lambda": lambda3_tiles, "bbox": bbox3_tiles, "linear": linear3_tiles,
+                "lambda_below": below3_tiles}[kind](nb)
     raise ValueError(m)
 
 

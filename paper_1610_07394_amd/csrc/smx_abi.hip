@@ -103,6 +103,9 @@ bool make_geom(int m, int64_t nb, int map, MapGeom &g) {
             g.main = uint32_t(main);
             g.G = main + g2;
         }
+    } else if (map == MAP_BELOW) {
+        if (nb > (int64_t(1) << 24)) return fail(SMX_EOVERFLOW, "grid too large (nb = %lld)", (long long)nb), false;
+        g.G = m == 2 ? below2_blocks(u) : below3_blocks(u);
     } else if (map == MAP_BBOX) {
         if (nb > kMaxGridDim) return fail(SMX_EUNSUPPORTED, "bounding-box grid dimension %lld > 65535", (long long)nb), false;
         g.G = m == 2 ? u * u : u * u * u;
@@ -118,7 +121,7 @@ static int check_common(int m, int64_t n, int rho, int map, int maxrho) {
     if (n < 0) return fail(SMX_EINVAL, "n must be >= 0 (got %lld)", (long long)n);
     if (n > kMaxN) return fail(SMX_EOVERFLOW, "n = %lld exceeds 2^31 - 1", (long long)n);
     if (!pow2(rho) || rho > maxrho) return fail(SMX_EINVAL, "rho must be a power of two in [1, %d] (got %d)", maxrho, rho);
-    if (map < 0 || map > 2) return fail(SMX_EINVAL, "unknown map %d", map);
+    if (map < 0 || map > 3) return fail(SMX_EINVAL, "unknown map %d", map);
     return SMX_OK;
 }
 
@@ -217,6 +220,7 @@ int smx_map_tiles_host(int m, int64_t n, int rho, int map, int64_t first, int64_
         if (m == 2) {
             if (map == MAP_LAMBDA) ok = lambda2(uint32_t(b), g.lg, g.nb, X, Y);
             else if (map == MAP_BBOX) { X = int(b % g.nb); Y = int(b / g.nb); ok = X <= Y; }
+            else if (map == MAP_BELOW) ok = below2(b, uint32_t(g.nb), X, Y);
             else { linear2(uint32_t(b), X, Y); ok = true; }
             o[0] = ok ? X : -1;
             o[1] = ok ? Y : -1;
@@ -225,7 +229,8 @@ int smx_map_tiles_host(int m, int64_t n, int rho, int map, int64_t first, int64_
             else if (map == MAP_BBOX) {
                 X = int(b % g.nb); Y = int((b / g.nb) % g.nb); Z = int(b / (uint64_t(g.nb) * g.nb));
                 ok = X <= Y && Y <= Z;
-            } else { linear3(uint32_t(b), X, Y, Z); ok = true; }
+            } else if (map == MAP_BELOW) ok = below3(b, uint32_t(g.nb), X, Y, Z);
+            else { linear3(uint32_t(b), X, Y, Z); ok = true; }
             o[0] = ok ? X : -1;
             o[1] = ok ? Y : -1;
             o[2] = ok ? Z : -1;
@@ -269,7 +274,7 @@ int smx_edm_packed(const float *d_X, int64_t n, int64_t d, int64_t ldx, int map,
     if (n > kMaxN) return fail(SMX_EOVERFLOW, "n exceeds 2^31 - 1");
     if (d < 1) return fail(SMX_EINVAL, "d must be >= 1 (got %lld)", (long long)d);
     if (ldx < d) return fail(SMX_EINVAL, "ldx (%lld) < d (%lld)", (long long)ldx, (long long)d);
-    if (map < 0 || map > 2) return fail(SMX_EINVAL, "unknown map %d", map);
+    if (map < 0 || map > 3) return fail(SMX_EINVAL, "unknown map %d", map);
     if (prec < 0 || prec > 2) return fail(SMX_EINVAL, "unknown precision %d", prec);
     if (n == 0) return SMX_OK;
     if (d_X == nullptr || d_D == nullptr) return fail(SMX_EINVAL, "X and D must not be NULL");
@@ -277,7 +282,7 @@ int smx_edm_packed(const float *d_X, int64_t n, int64_t d, int64_t ldx, int map,
     const bool need_ws = prec != SMX_EDM_FP32_DIFF || d_stats != nullptr;
     if (need_ws && (d_ws == nullptr || ws_bytes < w.total))
         return fail(SMX_EINVAL, "workspace of %zu bytes required (got %zu)", w.total, ws_bytes);
-    const int tile = prec == SMX_EDM_FP32_DIFF ? kEdmTile : kGramTile;
+    const int tile = prec == SMX_EDM_FP32_DIFF ? edm_diff_tile(n) : kGramTile;
     MapGeom g;
     if (!make_geom(2, (n + tile - 1) / tile, map, g)) return SMX_EOVERFLOW;
     char *ws = reinterpret_cast<char *>(d_ws);
@@ -286,7 +291,7 @@ int smx_edm_packed(const float *d_X, int64_t n, int64_t d, int64_t ldx, int map,
     if (slots && (rc = launch_fill_u64(reinterpret_cast<uint64_t *>(slots), kSlotBytes / 8, S(stream))))
         return rc;
     if (prec == SMX_EDM_FP32_DIFF) {
-        rc = launch_edm_diff(g, d_X, n, d, ldx, d_D, slots, S(stream));
+        rc = launch_edm_diff(g, tile, d_X, n, d, ldx, d_D, slots, S(stream));
     } else {
         const bool split = prec == SMX_EDM_SPLITBF16_GRAM;
         const int64_t dpad = (d + kGramK - 1) / kGramK * kGramK;
@@ -316,7 +321,7 @@ static int triplet_run(int mode, const float *d_X, int64_t n, int64_t ldx, const
     if (n < 0) return fail(SMX_EINVAL, "n must be >= 0");
     if (n > kMaxN) return fail(SMX_EOVERFLOW, "n exceeds 2^31 - 1");
     if (ldx < 3) return fail(SMX_EINVAL, "ldx must be >= 3 (got %lld)", (long long)ldx);
-    if (map < 0 || map > 2) return fail(SMX_EINVAL, "unknown map %d", map);
+    if (map < 0 || map > 3) return fail(SMX_EINVAL, "unknown map %d", map);
     int rc = check_pot(pot);
     if (rc) return rc;
     if (mode == 0 && d_E == nullptr) return fail(SMX_EINVAL, "E must not be NULL");

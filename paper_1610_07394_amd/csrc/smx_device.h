@@ -22,6 +22,48 @@ __device__ __forceinline__ uint64_t launch_index() {
     return uint64_t(blockIdx.y) * gridDim.x + blockIdx.x;
 }
 
+// Tile of this block under map MAP.  Returns false for a filtered block (and
+// for the tail of a 2-D launch, where lin >= G).  `lin` receives the logical
+// block index (the dump position).  XCD: renumber the dispatch order so that
+// each XCD takes one contiguous range of logical blocks.  The bounding box is
+// the hardware 2-D / 3-D grid itself (identity map, no renumbering).
+template <int MAP, bool XCD>
+__device__ __forceinline__ bool tile2_of(const MapGeom &g, uint64_t &lin, int &X, int &Y) {
+    if (MAP == MAP_BBOX) {
+        X = int(blockIdx.x);
+        Y = int(blockIdx.y);
+        lin = uint64_t(Y) * uint64_t(g.nb) + uint64_t(X);
+        return X <= Y;
+    }
+    lin = uint64_t(blockIdx.y) * gridDim.x + blockIdx.x;
+    if (lin >= g.G) return false;
+    const uint32_t id = XCD ? xcd_remap(uint32_t(lin), uint32_t(g.G)) : uint32_t(lin);
+    lin = id;
+    if (MAP == MAP_LAMBDA) return lambda2(id, g.lg, g.nb, X, Y);
+    if (MAP == MAP_BELOW) return below2(id, uint32_t(g.nb), X, Y);
+    linear2(id, X, Y);
+    return true;
+}
+
+template <int MAP, bool XCD>
+__device__ __forceinline__ bool tile3_of(const MapGeom &g, uint64_t &lin, int &X, int &Y, int &Z) {
+    if (MAP == MAP_BBOX) {
+        X = int(blockIdx.x);
+        Y = int(blockIdx.y);
+        Z = int(blockIdx.z);
+        lin = (uint64_t(Z) * uint64_t(g.nb) + uint64_t(Y)) * uint64_t(g.nb) + uint64_t(X);
+        return X <= Y && Y <= Z;
+    }
+    lin = uint64_t(blockIdx.y) * gridDim.x + blockIdx.x;
+    if (lin >= g.G) return false;
+    const uint32_t id = XCD ? xcd_remap(uint32_t(lin), uint32_t(g.G)) : uint32_t(lin);
+    lin = id;
+    if (MAP == MAP_LAMBDA) return lambda3(id, g.lg, g.nb, g.main, X, Y, Z);
+    if (MAP == MAP_BELOW) return below3(id, uint32_t(g.nb), X, Y, Z);
+    linear3(id, X, Y, Z);
+    return true;
+}
+
 // SplitMix64 finaliser (Steele, Lea, Flood, OOPSLA 2014): the output function
 // applied to state x + golden-ratio increment.
 __device__ __forceinline__ uint64_t mix64(uint64_t x) {

@@ -64,44 +64,36 @@ int launch_gram_prep(const float *X, int64_t n, int64_t d, int64_t ldx, int64_t 
     return check_launch("gram prep");
 }
 
-template <int MAP>
-__device__ __forceinline__ bool gram_tile(const MapGeom &g, uint64_t &lin, int &X, int &Y) {
-    if (MAP == MAP_BBOX) {
-        X = int(blockIdx.x);
-        Y = int(blockIdx.y);
-        lin = uint64_t(Y) * uint64_t(g.nb) + uint64_t(X);
-        return X <= Y;
-    }
-    lin = launch_index();
-    if (lin >= g.G) return false;
-    const uint32_t id = xcd_remap(uint32_t(lin), uint32_t(g.G));
-    lin = id;
-    if (MAP == MAP_LAMBDA) return lambda2(id, g.lg, g.nb, X, Y);
-    linear2(id, X, Y);
-    return true;
-}
+// Staging.  Every MFMA operand fragment travels from global memory straight
+// into LDS with global_load_lds_dwordx4: one wave load fills a 1 KB block,
+// lane s writing the 16 bytes it later reads back as its operand.  Block
+// (mb, ks) of a 128-row panel chunk holds rows mb*32 + (s & 31), k =
+// ks*16 + 8*(s >> 5) .. +7, so an operand read is base + 16*lane (no bank
+// conflicts) and staging costs no VGPRs.  Two LDS buffers alternate: a wave
+// reads all fragments of chunk s into registers, then issues the loads of
+// chunk s + 1 into the other buffer, then runs the MFMAs of chunk s while those
+// loads are in flight.
+template <bool SPLIT>
+struct GramCfg {
+    static constexpr int NARR = SPLIT ? 4 : 2;  // A_hi, B_hi, (A_lo, B_lo)
+    static constexpr int LPW = NARR * 8 / 4;    // wave loads per chunk per wave
+};
 
-// Global -> register staging of one K chunk: this thread's 16 bf16 (32 bytes)
-// of row ra_row (I panel) and rb_row (J panel), for hi and, when split, lo.
-template <int NP>
-__device__ __forceinline__ void gram_gload(uint4 (&ra)[NP][2], uint4 (&rb)[NP][2], const uint16_t *__restrict__ hi,
-                                           const uint16_t *__restrict__ lo, int64_t ra_row, int64_t rb_row,
-                                           int64_t n, int64_t dpad, int64_t kofs) {
+typedef uint4 GramBuf[8][64];  // one array's 128 x 32 chunk in fragment order
+
+template <bool SPLIT>
+__device__ __forceinline__ void gram_issue(GramBuf *buf, const uint16_t *__restrict__ hi,
+                                           const uint16_t *__restrict__ lo, int64_t I0, int64_t J0,
+                                           int64_t n, int64_t dpad, int64_t k0, int wave, int lane) {
 #pragma unroll
-    for (int p = 0; p < NP; ++p) {
-        const uint16_t *src = p == 0 ? hi : lo;
-        ra[p][0] = ra[p][1] = make_uint4(0, 0, 0, 0);
-        rb[p][0] = rb[p][1] = make_uint4(0, 0, 0, 0);
-        if (ra_row < n) {
-            const uint4 *q = reinterpret_cast<const uint4 *>(src + ra_row * dpad + kofs);
-            ra[p][0] = q[0];
-            ra[p][1] = q[1];
-        }
-        if (rb_row < n) {
-            const uint4 *q = reinterpret_cast<const uint4 *>(src + rb_row * dpad + kofs);
-            rb[p][0] = q[0];
-            rb[p][1] = q[1];
-        }
+    for (int t = 0; t < GramCfg<SPLIT>::LPW; ++t) {
+        const int gb = wave + 4 * t;  // 0 .. 8 NARR - 1
+        const int arr = gb >> 3, blk = gb & 7, mb = blk >> 1, ks = blk & 1;
+        const uint16_t *src = (arr & 2) ? lo : hi;
+        int64_t row = ((arr & 1) ? J0 : I0) + mb * 32 + (lane & 31);
+        row = row < n ? row : n - 1;  // rows past n load row n-1; their outputs are never stored
+        const uint16_t *g = src + row * dpad + k0 + ks * 16 + 8 * (lane >> 5);
+        __builtin_amdgcn_global_load_lds(g, &buf[arr][blk][0], 16, 0, 0);
     }
 }
 
@@ -114,10 +106,9 @@ __global__ __launch_bounds__(kGramThreads) void edm_gram_kernel(MapGeom g, const
                                                                unsigned long long *slots) {
     uint64_t lin;
     int TX, TY;
-    if (!gram_tile<MAP>(g, lin, TX, TY)) return;
-    constexpr int NP = SPLIT ? 2 : 1;
-    __shared__ __attribute__((aligned(16))) uint16_t As[NP][kGramTile * kGramLd];
-    __shared__ __attribute__((aligned(16))) uint16_t Bs[NP][kGramTile * kGramLd];
+    if (!tile2_of<MAP, true>(g, lin, TX, TY)) return;
+    constexpr int NARR = GramCfg<SPLIT>::NARR, NP = SPLIT ? 2 : 1;
+    __shared__ __attribute__((aligned(16))) GramBuf Lb[2][NARR];
     __shared__ float nA[kGramTile], nB[kGramTile];
 
     const int t = threadIdx.x;
@@ -128,11 +119,6 @@ __global__ __launch_bounds__(kGramThreads) void edm_gram_kernel(MapGeom g, const
     if (t < kGramTile) nA[t] = I0 + t < n ? norms[I0 + t] : 0.f;
     else nB[t - kGramTile] = J0 + t - kGramTile < n ? norms[J0 + t - kGramTile] : 0.f;
 
-    // global -> register staging: thread owns 16 bf16 (32 bytes) of one row
-    const int lrow = t >> 1, lhalf = t & 1;
-    const int64_t ra_row = I0 + lrow, rb_row = J0 + lrow;
-    uint4 ra[NP][2], rb[NP][2];
-
     f32x16_t acc[2][2];
 #pragma unroll
     for (int m = 0; m < 2; ++m)
@@ -141,44 +127,38 @@ __global__ __launch_bounds__(kGramThreads) void edm_gram_kernel(MapGeom g, const
 #pragma unroll
             for (int e = 0; e < 16; ++e) acc[m][c][e] = 0.f;
 
-    gram_gload<NP>(ra, rb, hi, lo, ra_row, rb_row, n, dpad, 16 * lhalf);
-    for (int64_t k0 = 0; k0 < dpad; k0 += kGramK) {
+    const int nst = int(dpad / kGramK);
+    gram_issue<SPLIT>(Lb[0], hi, lo, I0, J0, n, dpad, 0, w, lane);
+    for (int s = 0; s < nst; ++s) {
+        __builtin_amdgcn_s_waitcnt(0);  // this wave's loads of chunk s have landed
+        __syncthreads();                // ... and every wave's; chunk s - 1 is consumed
+        const GramBuf *cur = Lb[s & 1];
+        bf16x8_t a[2][NP][2], b[2][NP][2];  // [k-step][hi, lo][sub-tile]
 #pragma unroll
-        for (int p = 0; p < NP; ++p) {
-            uint4 *a = reinterpret_cast<uint4 *>(&As[p][lrow * kGramLd + 16 * lhalf]);
-            uint4 *b = reinterpret_cast<uint4 *>(&Bs[p][lrow * kGramLd + 16 * lhalf]);
-            a[0] = ra[p][0];
-            a[1] = ra[p][1];
-            b[0] = rb[p][0];
-            b[1] = rb[p][1];
-        }
-        __syncthreads();
-        if (k0 + kGramK < dpad) gram_gload<NP>(ra, rb, hi, lo, ra_row, rb_row, n, dpad, k0 + kGramK + 16 * lhalf);
-#pragma unroll
-        for (int ks = 0; ks < kGramK / 16; ++ks) {
-            const int kofs = ks * 16 + 8 * (lane >> 5);
-            bf16x8_t a[NP][2], b[NP][2];
+        for (int ks = 0; ks < 2; ++ks)
 #pragma unroll
             for (int p = 0; p < NP; ++p)
 #pragma unroll
                 for (int m = 0; m < 2; ++m) {
-                    a[p][m] = *reinterpret_cast<const bf16x8_t *>(
-                        &As[p][(wm * 64 + m * 32 + (lane & 31)) * kGramLd + kofs]);
-                    b[p][m] = *reinterpret_cast<const bf16x8_t *>(
-                        &Bs[p][(wn * 64 + m * 32 + (lane & 31)) * kGramLd + kofs]);
+                    a[ks][p][m] = __builtin_bit_cast(bf16x8_t, cur[2 * p][(wm * 2 + m) * 2 + ks][lane]);
+                    b[ks][p][m] = __builtin_bit_cast(bf16x8_t, cur[2 * p + 1][(wn * 2 + m) * 2 + ks][lane]);
                 }
+        if (s + 1 < nst)
+            gram_issue<SPLIT>(Lb[(s + 1) & 1], hi, lo, I0, J0, n, dpad, int64_t(s + 1) * kGramK, w, lane);
+#pragma unroll
+        for (int ks = 0; ks < 2; ++ks)
 #pragma unroll
             for (int m = 0; m < 2; ++m)
 #pragma unroll
                 for (int c = 0; c < 2; ++c) {
-                    acc[m][c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[0][m], b[0][c], acc[m][c], 0, 0, 0);
+                    acc[m][c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[ks][0][m], b[ks][0][c], acc[m][c], 0, 0, 0);
                     if (SPLIT) {
-                        acc[m][c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[0][m], b[1][c], acc[m][c], 0, 0, 0);
-                        acc[m][c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[1][m], b[0][c], acc[m][c], 0, 0, 0);
+                        acc[m][c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[ks][0][m], b[ks][NP - 1][c], acc[m][c],
+                                                                            0, 0, 0);
+                        acc[m][c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[ks][NP - 1][m], b[ks][0][c], acc[m][c],
+                                                                            0, 0, 0);
                     }
                 }
-        }
-        __syncthreads();
     }
 
     // 32 x 32 accumulator layout: lane l, element e holds row
@@ -211,7 +191,6 @@ __global__ __launch_bounds__(kGramThreads) void edm_gram_kernel(MapGeom g, const
         if (t == 0) stats_add(slots, lin, c, h);
     }
 }
-
 template <int MAP, bool SPLIT>
 static void go_gram(const MapGeom &g, const uint16_t *hi, const uint16_t *lo, const float *norms,
                     int64_t n, int64_t dpad, float *D, unsigned long long *slots, hipStream_t s) {
@@ -228,18 +207,11 @@ int launch_edm_gram(const MapGeom &g, const uint16_t *hi, const uint16_t *lo, co
                     int64_t n, int64_t dpad, bool split, float *D, unsigned long long *slots,
                     hipStream_t s) {
     prof_begin(K_EDM_GRAM, s);
-    const int map = int(g.map);
-#define SMX_GO(M)                                                            \
-    if (split) go_gram<M, true>(g, hi, lo, norms, n, dpad, D, slots, s); \
-    else go_gram<M, false>(g, hi, lo, norms, n, dpad, D, slots, s);
-    if (map == MAP_LAMBDA) {
-        SMX_GO(MAP_LAMBDA)
-    } else if (map == MAP_BBOX) {
-        SMX_GO(MAP_BBOX)
-    } else {
-        SMX_GO(MAP_LINEAR)
-    }
-#undef SMX_GO
+    map_switch(int(g.map), [&](auto M) {
+        constexpr int MAPK = decltype(M)::value;
+        if (split) go_gram<MAPK, true>(g, hi, lo, norms, n, dpad, D, slots, s);
+        else go_gram<MAPK, false>(g, hi, lo, norms, n, dpad, D, slots, s);
+    });
     prof_end(K_EDM_GRAM, s);
     return check_launch("edm_packed (gram)");
 }

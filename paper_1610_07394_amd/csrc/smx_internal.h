@@ -3,6 +3,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "smx.h"
 #include "smx_maps.h"
 
@@ -31,6 +33,18 @@ inline dim3 grid_for(uint64_t G, int threads) {
     return dim3(uint32_t(gx), uint32_t((G + gx - 1) / gx), 1);
 }
 
+// Call f(std::integral_constant<int, MAP>{}) for the runtime map kind, so each
+// launcher instantiates its kernel once per map.
+template <typename F>
+inline void map_switch(int map, F &&f) {
+    switch (map) {
+    case MAP_LAMBDA: f(std::integral_constant<int, MAP_LAMBDA>{}); break;
+    case MAP_BBOX: f(std::integral_constant<int, MAP_BBOX>{}); break;
+    case MAP_LINEAR: f(std::integral_constant<int, MAP_LINEAR>{}); break;
+    default: f(std::integral_constant<int, MAP_BELOW>{}); break;
+    }
+}
+
 // Map geometry for m-dimensional work with nb tiles per dimension.
 // Returns false (with an error set) when the grid does not fit the index types.
 bool make_geom(int m, int64_t nb, int map, MapGeom &g);
@@ -46,10 +60,12 @@ int launch_map2(const MapGeom &g, int64_t n, int rho, int map, int strict, int32
 int launch_map3(const MapGeom &g, int64_t n, int rho, int map, int strict, int32_t *tiles,
                 unsigned long long *slots, hipStream_t s);
 
-constexpr int kEdmTile = 64;     // FP32 difference form: 64 x 64 elements per block
+// FP32 difference form: 128 x 128 tiles (8 x 8 per thread) once there are
+// enough of them to fill the chip, 64 x 64 (4 x 4 per thread) below that.
+inline int edm_diff_tile(int64_t n) { return n >= 8192 ? 128 : 64; }
 constexpr int kGramTile = 128;   // Gram form: 128 x 128 elements per block
 constexpr int kGramK = 32;       // Gram K padding
-int launch_edm_diff(const MapGeom &g, const float *X, int64_t n, int64_t d, int64_t ldx, float *D,
+int launch_edm_diff(const MapGeom &g, int tile, const float *X, int64_t n, int64_t d, int64_t ldx, float *D,
                     unsigned long long *slots, hipStream_t s);
 int launch_gram_prep(const float *X, int64_t n, int64_t d, int64_t ldx, int64_t dpad, uint16_t *hi,
                      uint16_t *lo, float *norms, bool split, hipStream_t s);

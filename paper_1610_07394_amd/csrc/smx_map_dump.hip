@@ -50,47 +50,12 @@ int launch_stats_finalize(const unsigned long long *slots, uint64_t launched, in
     return check_launch("stats finalize");
 }
 
-// Resolve the tile of this block.  Returns false for a filtered block.  `lin`
-// receives the logical block index used for the dump position.
-template <int MAP>
-__device__ __forceinline__ bool block_tile2(const MapGeom &g, uint64_t &lin, int &X, int &Y) {
-    if (MAP == MAP_BBOX) {
-        X = int(blockIdx.x);
-        Y = int(blockIdx.y);
-        lin = uint64_t(Y) * uint64_t(g.nb) + uint64_t(X);
-        return X <= Y;
-    }
-    lin = launch_index();
-    if (lin >= g.G) return false;
-    const uint32_t id = uint32_t(lin);
-    if (MAP == MAP_LAMBDA) return lambda2(id, g.lg, g.nb, X, Y);
-    linear2(id, X, Y);
-    return true;
-}
-
-template <int MAP>
-__device__ __forceinline__ bool block_tile3(const MapGeom &g, uint64_t &lin, int &X, int &Y, int &Z) {
-    if (MAP == MAP_BBOX) {
-        X = int(blockIdx.x);
-        Y = int(blockIdx.y);
-        Z = int(blockIdx.z);
-        lin = (uint64_t(Z) * uint64_t(g.nb) + uint64_t(Y)) * uint64_t(g.nb) + uint64_t(X);
-        return X <= Y && Y <= Z;
-    }
-    lin = launch_index();
-    if (lin >= g.G) return false;
-    const uint32_t id = uint32_t(lin);
-    if (MAP == MAP_LAMBDA) return lambda3(id, g.lg, g.nb, g.main, X, Y, Z);
-    linear3(id, X, Y, Z);
-    return true;
-}
-
 template <int MAP, bool STRICT>
 __global__ __launch_bounds__(kMapThreads) void map2_kernel(MapGeom g, int64_t n, int rho, int lgrho,
                                                           int32_t *tiles, unsigned long long *slots) {
     uint64_t lin;
     int X = -1, Y = -1;
-    const bool ok = block_tile2<MAP>(g, lin, X, Y);
+    const bool ok = tile2_of<MAP, false>(g, lin, X, Y);
     if (MAP != MAP_BBOX && lin >= g.G) return;  // tail of a 2-D launch
     if (tiles != nullptr && threadIdx.x == 0) {
         tiles[2 * lin + 0] = ok ? X : -1;
@@ -119,7 +84,7 @@ __global__ __launch_bounds__(kMapThreads) void map3_kernel(MapGeom g, int64_t n,
                                                           int32_t *tiles, unsigned long long *slots) {
     uint64_t lin;
     int X = -1, Y = -1, Z = -1;
-    const bool ok = block_tile3<MAP>(g, lin, X, Y, Z);
+    const bool ok = tile3_of<MAP, false>(g, lin, X, Y, Z);
     if (MAP != MAP_BBOX && lin >= g.G) return;
     if (tiles != nullptr && threadIdx.x == 0) {
         tiles[3 * lin + 0] = ok ? X : -1;
@@ -172,9 +137,7 @@ int launch_map2(const MapGeom &g, int64_t n, int rho, int map, int strict, int32
                 unsigned long long *slots, hipStream_t s) {
     const int lgrho = floor_log2_u32(uint32_t(rho));
     prof_begin(K_MAP2, s);
-    if (map == MAP_LAMBDA) go_map2<MAP_LAMBDA>(g, n, rho, lgrho, strict, tiles, slots, s);
-    else if (map == MAP_BBOX) go_map2<MAP_BBOX>(g, n, rho, lgrho, strict, tiles, slots, s);
-    else go_map2<MAP_LINEAR>(g, n, rho, lgrho, strict, tiles, slots, s);
+    map_switch(map, [&](auto M) { go_map2<decltype(M)::value>(g, n, rho, lgrho, strict, tiles, slots, s); });
     prof_end(K_MAP2, s);
     return check_launch("simplex_map2");
 }
@@ -183,9 +146,7 @@ int launch_map3(const MapGeom &g, int64_t n, int rho, int map, int strict, int32
                 unsigned long long *slots, hipStream_t s) {
     const int lgrho = floor_log2_u32(uint32_t(rho));
     prof_begin(K_MAP3, s);
-    if (map == MAP_LAMBDA) go_map3<MAP_LAMBDA>(g, n, rho, lgrho, strict, tiles, slots, s);
-    else if (map == MAP_BBOX) go_map3<MAP_BBOX>(g, n, rho, lgrho, strict, tiles, slots, s);
-    else go_map3<MAP_LINEAR>(g, n, rho, lgrho, strict, tiles, slots, s);
+    map_switch(map, [&](auto M) { go_map3<decltype(M)::value>(g, n, rho, lgrho, strict, tiles, slots, s); });
     prof_end(K_MAP3, s);
     return check_launch("simplex_map3");
 }

@@ -19,7 +19,7 @@
 
 namespace smx {
 
-enum MapKind { MAP_LAMBDA = 0, MAP_BBOX = 1, MAP_LINEAR = 2 };
+enum MapKind { MAP_LAMBDA = 0, MAP_BBOX = 1, MAP_LINEAR = 2, MAP_BELOW = 3 };
 
 // floor(log2 v), v >= 1.  The paper's bit-level form (Sec. III-A) counts from
 // the word size W: floor(log2 v) = (W - 1) - clz(v), 2^floor(log2 v) = 1 << that.
@@ -190,6 +190,102 @@ SMX_HD void linear3(uint32_t k, int &X, int &Y, int &Z) {
     Z = int(z);
     Y = int(y);
     X = int(r - tri_u64(y));
+}
+
+// ---------------------------------------------------------------- from below
+// "Approach n from below" (Sec. III-A): nb is split into its binary digits,
+// largest first, segments [o, o + m) with m = 2^floor(log2 rest).  All sizes
+// below are powers of two, so the lambda maps inside them filter nothing in 2-D.
+//   2-simplex, per segment: lambda2 of m on its diagonal triangle, then the
+//     rectangle [o, o + m) x [o + m, nb) under the identity (x fastest).
+//   3-simplex, per segment: lambda3 of m (its tetrahedron), then the prism
+//     {x <= y in the segment, z above} = lambda2(m) x identity, then the prism
+//     {x in the segment, y <= z above} = identity x (2-simplex from below of
+//     the rest).
+// Decoding walks the segments (at most popcount(nb) steps, block uniform).
+SMX_HD uint64_t below2_blocks(uint64_t nb) { return nb * (nb + 1) / 2; }
+
+SMX_HD bool below2(uint64_t id, uint32_t nb, int &X, int &Y) {
+    uint32_t o = 0, rem = nb;
+    while (rem != 0) {
+        const int L = floor_log2_u32(rem);
+        const uint32_t m = 1u << L, r = rem - m;
+        const uint64_t tri = uint64_t(m) * (m + 1) / 2;
+        if (id < tri) {
+            int x, y;
+            lambda2(uint32_t(id), L, int(m), x, y);
+            X = int(o) + x;
+            Y = int(o) + y;
+            return true;
+        }
+        id -= tri;
+        const uint64_t rect = uint64_t(m) * r;
+        if (id < rect) {
+            X = int(o + uint32_t(id & (m - 1)));
+            Y = int(o + m + uint32_t(id >> L));
+            return true;
+        }
+        id -= rect;
+        o += m;
+        rem = r;
+    }
+    return false;
+}
+
+SMX_HD uint64_t below3_blocks(uint64_t nb) {
+    uint64_t tot = 0, rem = nb;
+    while (rem != 0) {
+        int L = 0;
+        while ((uint64_t(2) << L) <= rem) ++L;
+        const uint64_t m = uint64_t(1) << L, r = rem - m;
+        tot += lambda3_main_blocks(L) + lambda2_blocks(L) + lambda2_blocks(L) * r + m * (r * (r + 1) / 2);
+        rem = r;
+    }
+    return tot;
+}
+
+SMX_HD bool below3(uint64_t id, uint32_t nb, int &X, int &Y, int &Z) {
+    uint32_t o = 0, rem = nb;
+    while (rem != 0) {
+        const int L = floor_log2_u32(rem);
+        const uint32_t m = 1u << L, r = rem - m;
+        const uint32_t main = lambda3_main_blocks(L);
+        const uint64_t p2 = lambda2_blocks(L);
+        const uint64_t tet = uint64_t(main) + p2;
+        if (id < tet) {
+            int x, y, z;
+            if (!lambda3(uint32_t(id), L, int(m), main, x, y, z)) return false;
+            X = int(o) + x;
+            Y = int(o) + y;
+            Z = int(o) + z;
+            return true;
+        }
+        id -= tet;
+        const uint64_t pa = p2 * r;
+        if (id < pa) {
+            const uint64_t z = id / p2;
+            int x, y;
+            lambda2(uint32_t(id - z * p2), L, int(m), x, y);
+            X = int(o) + x;
+            Y = int(o) + y;
+            Z = int(o + m + uint32_t(z));
+            return true;
+        }
+        id -= pa;
+        const uint64_t pb = uint64_t(m) * (uint64_t(r) * (r + 1) / 2);
+        if (id < pb) {
+            int y, z;
+            below2(id >> L, r, y, z);
+            X = int(o + uint32_t(id & (m - 1)));
+            Y = int(o + m) + y;
+            Z = int(o + m) + z;
+            return true;
+        }
+        id -= pb;
+        o += m;
+        rem = r;
+    }
+    return false;
 }
 
 // ---------------------------------------------------------------- XCD order

@@ -23,11 +23,15 @@
 //      of order (i >= j, j >= k, i >= k) or past n, which zeroes R for every
 //      triplet containing it -- the simplex mask costs nothing per triplet and
 //      diagonal tiles run the same code;
-//   3. thread (ib, jb, kb) = (lane / 8, lane % 8, wave) runs 4 i x 4 j x 8 k;
-//      its k order is rotated by (ib + jb) so that the per-k pair weights it
-//      adds to LDS (ds_add_f32) never share an address within one instruction;
+//   3. each thread runs 4 i x 4 j x 8 k (wave kb owns k in [8 kb, 8 kb + 8));
+//      per k, the weights W_ik and W_jk are summed across lanes with DPP
+//      (quad_perm within a quad, row_ror 4 / 8 across a row's quads) and each
+//      entry is stored once into one of two half-wave planes; W_ij stays in
+//      registers and each wave stores its own slice after the loop.  LDS
+//      atomics cost far more than these shuffles on gfx950, and none remain;
 //   4. pair weights -> forces on the 96 particles (64 pair terms each, two
-//      threads per particle), FP64 atomics into the gradient;
+//      threads per particle; the planes and slices are summed on read), FP64
+//      atomics into the gradient;
 //   5. energy: wave / block sums in FP64, one atomic into a spread slot.
 #include "smx_device.h"
 #include "smx_internal.h"
@@ -37,38 +41,41 @@ namespace smx {
 constexpr int kTripThreads = 256;
 constexpr int kTripLd = kTripTile + 4;  // LDS row stride (floats)
 
-template <int MAP>
-__device__ __forceinline__ bool trip_tile(const MapGeom &g, uint64_t &lin, int &X, int &Y, int &Z) {
-    if (MAP == MAP_BBOX) {
-        X = int(blockIdx.x);
-        Y = int(blockIdx.y);
-        Z = int(blockIdx.z);
-        lin = (uint64_t(Z) * uint64_t(g.nb) + uint64_t(Y)) * uint64_t(g.nb) + uint64_t(X);
-        return X <= Y && Y <= Z;
-    }
-    lin = launch_index();
-    if (lin >= g.G) return false;
-    const uint32_t id = xcd_remap(uint32_t(lin), uint32_t(g.G));
-    lin = id;
-    if (MAP == MAP_LAMBDA) return lambda3(id, g.lg, g.nb, g.main, X, Y, Z);
-    linear3(id, X, Y, Z);
-    return true;
+// DPP lane moves (all 64 lanes active): quad_perm xor 1 / xor 2 and
+// row_ror 4 / 8 within a 16-lane row.
+template <int CTRL>
+__device__ __forceinline__ float dpp_mov(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+// Sum over the 4 lanes of a quad; every lane gets the sum.
+__device__ __forceinline__ float quad_allsum(float v) {
+    v += dpp_mov<0xB1>(v);  // quad_perm [1,0,3,2]
+    v += dpp_mov<0x4E>(v);  // quad_perm [2,3,0,1]
+    return v;
+}
+// Sum over lanes l, l+4, l+8, l+12 (mod 16) of a row; every lane gets the sum.
+__device__ __forceinline__ float rowquads_allsum(float v) {
+    v += dpp_mov<0x124>(v);  // row_ror:4
+    v += dpp_mov<0x128>(v);  // row_ror:8
+    return v;
 }
 
 template <int MAP, bool GRAD, bool STATS>
-__global__ __launch_bounds__(kTripThreads) void at_kernel(MapGeom g, const float *__restrict__ Xp, int64_t n,
+__global__ __launch_bounds__(kTripThreads, 3) void at_kernel(MapGeom g, const float *__restrict__ Xp, int64_t n,
                                                           int64_t ldx, float nu, double *__restrict__ G64,
                                                           double *__restrict__ eslots,
                                                           unsigned long long *sslots) {
     uint64_t lin;
     int TX, TY, TZ;
-    if (!trip_tile<MAP>(g, lin, TX, TY, TZ)) return;
+    if (!tile3_of<MAP, true>(g, lin, TX, TY, TZ)) return;
 
     constexpr int PS = kTripTile * kTripLd;
     __shared__ float4 Pos[3][kTripTile];
-    __shared__ __attribute__((aligned(16))) float S[3][PS];   // 0: [i][j]  1: [k][i]  2: [k][j]
-    __shared__ __attribute__((aligned(16))) float Dv[3][PS];
-    __shared__ __attribute__((aligned(16))) float W[GRAD ? 3 : 1][GRAD ? PS : 1];
+    // SD[0..2]: pair terms s ([i][j], [k][i], [k][j]); SD[3..5]: d = 1/r of the same
+    // pairs.  After the triplet loop SD[0..3] hold the four per-wave slices of W_ij.
+    __shared__ __attribute__((aligned(16))) float SD[6][PS];
+    // per-k weights W_ik ([plane][k][i]) and W_jk ([plane][k][j]), two planes each
+    __shared__ __attribute__((aligned(16))) float WZ[GRAD ? 4 : 1][GRAD ? PS : 1];
     __shared__ double red[kTripThreads / kWave];
     __shared__ unsigned long long sred[2][kTripThreads / kWave];
 
@@ -86,13 +93,11 @@ __global__ __launch_bounds__(kTripThreads) void at_kernel(MapGeom g, const float
         }
         Pos[tile][a] = v;
     }
-    if (GRAD)
-        for (int e = t; e < 3 * PS; e += kTripThreads) (&W[0][0])[e] = 0.f;
     __syncthreads();
 
     // pair terms: set 0 rows i (X) cols j (Y); set 1 rows k (Z) cols i (X);
-    // set 2 rows k (Z) cols j (Y).  Valid iff col index < row index order of
-    // the triplet (i < j, i < k, j < k) and the larger one < n.
+    // set 2 rows k (Z) cols j (Y).  Valid iff the pair is in triplet order
+    // (i < j, i < k, j < k) and the larger index is < n.
     for (int e = t; e < 3 * kTripTile * kTripTile; e += kTripThreads) {
         const int set = e >> 10, r = (e >> 5) & 31, c = e & 31;
         const int ta = set == 0 ? 0 : 2, tb = set == 2 ? 1 : (set == 0 ? 1 : 0);
@@ -100,19 +105,21 @@ __global__ __launch_bounds__(kTripThreads) void at_kernel(MapGeom g, const float
         const float dx = pb.x - pa.x, dy = pb.y - pa.y, dz = pb.z - pa.z;
         const float s = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dx * dx));
         const int64_t ga = base[ta] + r, gb = base[tb] + c;
-        // set 0: (i = ga, j = gb) needs i < j; sets 1, 2: (k = ga, i/j = gb) needs gb < ga
         const bool valid = set == 0 ? (ga < gb && gb < n) : (gb < ga && ga < n);
-        S[set][r * kTripLd + c] = s;
-        Dv[set][r * kTripLd + c] = valid ? __builtin_amdgcn_rsqf(s) : 0.f;
+        SD[set][r * kTripLd + c] = s;
+        SD[3 + set][r * kTripLd + c] = valid ? __builtin_amdgcn_rsqf(s) : 0.f;
     }
     __syncthreads();
 
-    const int lane = t & 63, kb = t >> 6, ib = lane >> 3, jb = lane & 7;
+    // lane = 16 row + 4 q + e;  ib = 4 (row >> 1) + q,  jb = 4 (row & 1) + e;
+    // the thread owns i in 4 ib + [0,4), j in 4 jb + [0,4), k in 8 kb + [0,8)
+    const int lane = t & 63, kb = t >> 6, row = lane >> 4, q = (lane >> 2) & 3, el = lane & 3;
+    const int ib = 4 * (row >> 1) + q, jb = 4 * (row & 1) + el;
     float s1[4][4], d1[4][4], w1[4][4];
 #pragma unroll
     for (int a = 0; a < 4; ++a) {
-        const float4 sv = *reinterpret_cast<const float4 *>(&S[0][(4 * ib + a) * kTripLd + 4 * jb]);
-        const float4 dv = *reinterpret_cast<const float4 *>(&Dv[0][(4 * ib + a) * kTripLd + 4 * jb]);
+        const float4 sv = *reinterpret_cast<const float4 *>(&SD[0][(4 * ib + a) * kTripLd + 4 * jb]);
+        const float4 dv = *reinterpret_cast<const float4 *>(&SD[3][(4 * ib + a) * kTripLd + 4 * jb]);
         s1[a][0] = sv.x; s1[a][1] = sv.y; s1[a][2] = sv.z; s1[a][3] = sv.w;
         d1[a][0] = dv.x; d1[a][1] = dv.y; d1[a][2] = dv.z; d1[a][3] = dv.w;
 #pragma unroll
@@ -123,11 +130,11 @@ __global__ __launch_bounds__(kTripThreads) void at_kernel(MapGeom g, const float
 
 #pragma unroll 1
     for (int r = 0; r < 8; ++r) {
-        const int k = 8 * kb + ((r + ib + jb) & 7);
-        const float4 s3v = *reinterpret_cast<const float4 *>(&S[1][k * kTripLd + 4 * ib]);
-        const float4 d3v = *reinterpret_cast<const float4 *>(&Dv[1][k * kTripLd + 4 * ib]);
-        const float4 s2v = *reinterpret_cast<const float4 *>(&S[2][k * kTripLd + 4 * jb]);
-        const float4 d2v = *reinterpret_cast<const float4 *>(&Dv[2][k * kTripLd + 4 * jb]);
+        const int k = 8 * kb + r;
+        const float4 s3v = *reinterpret_cast<const float4 *>(&SD[1][k * kTripLd + 4 * ib]);
+        const float4 d3v = *reinterpret_cast<const float4 *>(&SD[4][k * kTripLd + 4 * ib]);
+        const float4 s2v = *reinterpret_cast<const float4 *>(&SD[2][k * kTripLd + 4 * jb]);
+        const float4 d2v = *reinterpret_cast<const float4 *>(&SD[5][k * kTripLd + 4 * jb]);
         const float s3a[4] = {s3v.x, s3v.y, s3v.z, s3v.w}, d3a[4] = {d3v.x, d3v.y, d3v.z, d3v.w};
         const float s2a[4] = {s2v.x, s2v.y, s2v.z, s2v.w}, d2a[4] = {d2v.x, d2v.y, d2v.z, d2v.w};
         float w2[4] = {0.f, 0.f, 0.f, 0.f}, w3[4] = {0.f, 0.f, 0.f, 0.f};
@@ -175,17 +182,19 @@ __global__ __launch_bounds__(kTripThreads) void at_kernel(MapGeom g, const float
                 }
             }
         if (GRAD) {
+            // W_ik: sum the lane's partials over the quad (jb low bits); lane el
+            // stores i = 4 ib + el into plane (row & 1).  W_jk: sum over the
+            // row's quads (ib low bits); lane q stores j = 4 jb + q into plane
+            // (row >> 1).  Each entry has exactly one writer: no atomics.
 #pragma unroll
-            for (int a = 0; a < 4; ++a) atomicAdd(&W[1][k * kTripLd + 4 * ib + a], w3[a]);
+            for (int a = 0; a < 4; ++a) w3[a] = quad_allsum(w3[a]);
 #pragma unroll
-            for (int b = 0; b < 4; ++b) atomicAdd(&W[2][k * kTripLd + 4 * jb + b], w2[b]);
+            for (int b = 0; b < 4; ++b) w2[b] = rowquads_allsum(w2[b]);
+            const float v3 = el == 0 ? w3[0] : (el == 1 ? w3[1] : (el == 2 ? w3[2] : w3[3]));
+            const float v2 = q == 0 ? w2[0] : (q == 1 ? w2[1] : (q == 2 ? w2[2] : w2[3]));
+            WZ[row & 1][k * kTripLd + 4 * ib + el] = v3;
+            WZ[2 + (row >> 1)][k * kTripLd + 4 * jb + q] = v2;
         }
-    }
-    if (GRAD) {
-#pragma unroll
-        for (int a = 0; a < 4; ++a)
-#pragma unroll
-            for (int b = 0; b < 4; ++b) atomicAdd(&W[0][(4 * ib + a) * kTripLd + 4 * jb + b], w1[a][b]);
     }
 
     // energy of the block, FP64 from the per-thread FP32 partials
@@ -198,27 +207,45 @@ __global__ __launch_bounds__(kTripThreads) void at_kernel(MapGeom g, const float
     }
 
     if (GRAD) {
+        // every wave is past the triplet loop (block_sum synchronised): the pair
+        // terms are dead, so SD[kb] takes this wave's slice of W_ij
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+            *reinterpret_cast<float4 *>(&SD[kb][(4 * ib + a) * kTripLd + 4 * jb]) =
+                make_float4(w1[a][0], w1[a][1], w1[a][2], w1[a][3]);
         __syncthreads();
         // particle p = t / 2 of the 96 (tile = p / 32), half h = t % 2:
-        //   X (i): h0 sum_j W[0][i][j] (x_i - x_j),  h1 sum_k W[1][k][i] (x_i - x_k)
-        //   Y (j): h0 sum_i W[0][i][j] (x_j - x_i),  h1 sum_k W[2][k][j] (x_j - x_k)
-        //   Z (k): h0 sum_i W[1][k][i] (x_k - x_i),  h1 sum_j W[2][k][j] (x_k - x_j)
+        //   X (i): h0 sum_j W_ij (x_i - x_j),  h1 sum_k W_ik (x_i - x_k)
+        //   Y (j): h0 sum_i W_ij (x_j - x_i),  h1 sum_k W_jk (x_j - x_k)
+        //   Z (k): h0 sum_i W_ik (x_k - x_i),  h1 sum_j W_jk (x_k - x_j)
         if (t < 2 * 3 * kTripTile) {
             const int p = t >> 1, h = t & 1, tile = p >> 5, a = p & 31;
             const float4 me = Pos[tile][a];
             float gx = 0.f, gy = 0.f, gz = 0.f;
-            int other, set;
-            bool row_is_me;  // W[set] indexed [me][other] (true) or [other][me]
-            if (tile == 0) { other = h == 0 ? 1 : 2; set = h == 0 ? 0 : 1; row_is_me = h == 0; }
-            else if (tile == 1) { other = h == 0 ? 0 : 2; set = h == 0 ? 0 : 2; row_is_me = false; }
-            else { other = h == 0 ? 0 : 1; set = h == 0 ? 1 : 2; row_is_me = true; }
-#pragma unroll 8
+            int other;
+            if (tile == 0) other = h == 0 ? 1 : 2;
+            else if (tile == 1) other = h == 0 ? 0 : 2;
+            else other = h == 0 ? 0 : 1;
+#pragma unroll 4
             for (int b = 0; b < kTripTile; ++b) {
-                const float wgt = row_is_me ? W[set][a * kTripLd + b] : W[set][b * kTripLd + a];
-                const float4 o = Pos[other][b];
-                gx = __builtin_fmaf(wgt, me.x - o.x, gx);
-                gy = __builtin_fmaf(wgt, me.y - o.y, gy);
-                gz = __builtin_fmaf(wgt, me.z - o.z, gz);
+                float wgt;
+                if (tile == 0 && h == 0) {
+                    const int o = a * kTripLd + b;
+                    wgt = (SD[0][o] + SD[1][o]) + (SD[2][o] + SD[3][o]);
+                } else if (tile == 1 && h == 0) {
+                    const int o = b * kTripLd + a;
+                    wgt = (SD[0][o] + SD[1][o]) + (SD[2][o] + SD[3][o]);
+                } else if ((tile == 0 && h == 1) || (tile == 2 && h == 0)) {
+                    const int o = tile == 0 ? b * kTripLd + a : a * kTripLd + b;  // W_ik stored [k][i]
+                    wgt = WZ[0][o] + WZ[1][o];
+                } else {
+                    const int o = tile == 1 ? b * kTripLd + a : a * kTripLd + b;  // W_jk stored [k][j]
+                    wgt = WZ[2][o] + WZ[3][o];
+                }
+                const float4 ot = Pos[other][b];
+                gx = __builtin_fmaf(wgt, me.x - ot.x, gx);
+                gy = __builtin_fmaf(wgt, me.y - ot.y, gy);
+                gz = __builtin_fmaf(wgt, me.z - ot.z, gz);
             }
             gx += __shfl_xor(gx, 1, kWave);
             gy += __shfl_xor(gy, 1, kWave);
@@ -250,18 +277,11 @@ int launch_triplet(const MapGeom &g, const float *X, int64_t n, int64_t ldx, flo
                    double *G64, double *eslots, unsigned long long *sslots, hipStream_t s) {
     const int kid = grad ? K_TRIP_GRAD : K_TRIP_ENERGY;
     prof_begin(kid, s);
-    const int map = int(g.map);
-#define SMX_GO(M)                                                   \
-    if (grad) go_at<M, true>(g, X, n, ldx, nu, G64, eslots, sslots, s); \
-    else go_at<M, false>(g, X, n, ldx, nu, G64, eslots, sslots, s);
-    if (map == MAP_LAMBDA) {
-        SMX_GO(MAP_LAMBDA)
-    } else if (map == MAP_BBOX) {
-        SMX_GO(MAP_BBOX)
-    } else {
-        SMX_GO(MAP_LINEAR)
-    }
-#undef SMX_GO
+    map_switch(int(g.map), [&](auto M) {
+        constexpr int MAPK = decltype(M)::value;
+        if (grad) go_at<MAPK, true>(g, X, n, ldx, nu, G64, eslots, sslots, s);
+        else go_at<MAPK, false>(g, X, n, ldx, nu, G64, eslots, sslots, s);
+    });
     prof_end(kid, s);
     return check_launch(grad ? "triplet energy+grad" : "triplet energy");
 }
@@ -280,22 +300,7 @@ __global__ __launch_bounds__(kLjThreads) void lj_kernel(MapGeom g, const float *
                                                         unsigned long long *sslots) {
     uint64_t lin;
     int TX, TY;
-    if (MAP == MAP_BBOX) {
-        TX = int(blockIdx.x);
-        TY = int(blockIdx.y);
-        lin = uint64_t(TY) * uint64_t(g.nb) + uint64_t(TX);
-        if (TX > TY) return;
-    } else {
-        lin = launch_index();
-        if (lin >= g.G) return;
-        const uint32_t id = xcd_remap(uint32_t(lin), uint32_t(g.G));
-        lin = id;
-        if (MAP == MAP_LAMBDA) {
-            if (!lambda2(id, g.lg, g.nb, TX, TY)) return;
-        } else {
-            linear2(id, TX, TY);
-        }
-    }
+    if (!tile2_of<MAP, true>(g, lin, TX, TY)) return;
     __shared__ float4 Pi[kLjTile], Pj[kLjTile];
     __shared__ float Fi[kLjTile][3], Fj[kLjTile][3];
     __shared__ double red[kLjThreads / kWave];
@@ -397,10 +402,7 @@ int launch_lj(const MapGeom &g, const float *X, int64_t n, int64_t ldx, float ep
               float rc2, double *G64, double *eslots, unsigned long long *sslots, hipStream_t s) {
     prof_begin(K_LJ, s);
     const float sig2 = sigma * sigma;
-    const int map = int(g.map);
-    if (map == MAP_LAMBDA) go_lj<MAP_LAMBDA>(g, X, n, ldx, eps, sig2, rc2, G64, eslots, sslots, s);
-    else if (map == MAP_BBOX) go_lj<MAP_BBOX>(g, X, n, ldx, eps, sig2, rc2, G64, eslots, sslots, s);
-    else go_lj<MAP_LINEAR>(g, X, n, ldx, eps, sig2, rc2, G64, eslots, sslots, s);
+    map_switch(int(g.map), [&](auto M) { go_lj<decltype(M)::value>(g, X, n, ldx, eps, sig2, rc2, G64, eslots, sslots, s); });
     prof_end(K_LJ, s);
     return check_launch("lennard-jones");
 }

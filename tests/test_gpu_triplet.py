@@ -127,8 +127,9 @@ def test_ldx4_input():
 
 def test_gradient_finite_differences_n64():
     """GPU gradient against 4th-order central differences of the oracle's FP64
-    energy (h = 2^-10, exactly representable on these FP32 coordinates)."""
-    X = _pts(64, seed=64)
+    energy (h = 2^-10).  Coordinates are snapped to multiples of 2^-12 (< 32,
+    so 17 significant bits), which makes every perturbed coordinate exact."""
+    X = (np.round(_pts(64, seed=64).astype(np.float64) * 4096) / 4096).astype(np.float32)
     _, G = smx.triplet_energy_grad(_gpu(X), AT)
     G = G.cpu().numpy().astype(np.float64)
     h = 2.0 ** -10
