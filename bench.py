@@ -34,6 +34,13 @@ PEAK_BF16 = 2.5e15         # FLOP/s, dense MFMA
 AT_FLOPS_FWD, AT_FLOPS_FWD_BWD = 20, 80   # declared flops per triplet
 LJ_FLOPS = 30                              # declared flops per pair (fwd + bwd)
 
+# HBM bytes per launch of the Axilrod-Teller gradient kernel from the two
+# rocprofv3 PMC passes (FETCH_SIZE, WRITE_SIZE, scaled by a 1 GiB copy) recorded
+# in profiles/step_lambda_hbm_traffic_pmc.md.  They describe the kernel built
+# from sources with this hash; once those change the figure is reported as null.
+AT_TRAFFIC = {"src_sha16": "e96bd42139604127", "fetch_bytes": 0.003e9, "write_bytes": 19.647e9}
+AT_SOURCES = ("smx_triplet.hip", "smx_device.h", "smx_maps.h")
+
 N_EDM, D_EDM = 65536, 64
 N_GRAM, D_GRAM = 32768, 512
 N_AT = 8192
@@ -160,8 +167,12 @@ def main():
     if dom == "triplet_grad":
         t = kavg[dom] / 1e3
         ach = AT_FLOPS_FWD_BWD * math.comb(N_AT, 3) / t
+        traffic = at_traffic()
         roof = {"kernel": "at_kernel<lambda, grad>", "bound": "alu", "achieved": ach / 1e12,
-                "peak": PEAK_FP32 / 1e12, "unit": "TFLOP/s", "frac": ach / PEAK_FP32, "traffic": None,
+                "peak": PEAK_FP32 / 1e12, "unit": "TFLOP/s", "frac": ach / PEAK_FP32,
+                "traffic": None if traffic is None else traffic[0] + traffic[1],
+                "traffic_fetch_bytes": None if traffic is None else traffic[0],
+                "traffic_write_bytes": None if traffic is None else traffic[1],
                 "per_unit": "80 flops per triplet (20 forward + 60 backward), 9.159e10 triplets per launch"}
     elif dom == "edm_diff":
         t = kavg[dom] / 1e3
@@ -243,6 +254,20 @@ def main():
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))
+
+
+def at_traffic():
+    """(fetch, write) HBM bytes per AT gradient launch, or None if the kernel
+    sources changed since the counters were taken."""
+    import hashlib
+    csrc = os.path.join(ROOT, "paper_1610_07394_amd", "csrc")
+    h = hashlib.sha256()
+    for f in AT_SOURCES:
+        with open(os.path.join(csrc, f), "rb") as fh:
+            h.update(fh.read())
+    if h.hexdigest()[:16] != AT_TRAFFIC["src_sha16"]:
+        return None
+    return AT_TRAFFIC["fetch_bytes"], AT_TRAFFIC["write_bytes"]
 
 
 def cpu_baseline(only, elements, total_elems):
