@@ -208,19 +208,25 @@ def main():
                 sp[k] = compare["bbox"][k] / compare["lambda"][k]
         compare["speedup_lambda_vs_bbox"] = sp
         # map-only parallel spaces (paper-like granularity: rho = 16 pairs, rho = 8 triplets)
+        # "visit" = every element of every mapped tile is touched (count + id
+        # checksum); "count" = each mapped block adds its tile's closed-form
+        # count, so the time is the map plus the launched blocks alone.
         mo = {}
-        for kind in ("lambda", "bbox", "linear"):
+        for kind in ("lambda", "bbox", "linear", "lambda_below"):
             for m, n, rho in ((2, N_EDM, 16), (3, N_AT, 8)):
-                fn = smx.simplex_map2 if m == 2 else smx.simplex_map3
-                fn(n, rho, kind, strict=(m == 3), tiles=False)
-                torch.cuda.synchronize()
-                smx.profile_enable(True)
-                smx.profile_reset()
-                for _ in range(3):
-                    fn(n, rho, kind, strict=(m == 3), tiles=False)
-                ms, c = smx.profile_read("map2" if m == 2 else "map3")
-                smx.profile_enable(False)
-                mo[f"map{m}_{kind}_n{n}_rho{rho}_ms"] = ms / c
+                visit = smx.simplex_map2 if m == 2 else smx.simplex_map3
+                runs = (("visit", lambda: visit(n, rho, kind, strict=(m == 3), tiles=False)),
+                        ("count", lambda: smx.simplex_count(m, n, rho, kind, strict=(m == 3))))
+                for what, fn in runs:
+                    fn()
+                    torch.cuda.synchronize()
+                    smx.profile_enable(True)
+                    smx.profile_reset()
+                    for _ in range(3):
+                        fn()
+                    ms, c = smx.profile_read("map2" if m == 2 else "map3")
+                    smx.profile_enable(False)
+                    mo[f"{what}{m}_{kind}_n{n}_rho{rho}_ms"] = ms / c
         compare["map_only"] = mo
 
     # ---- CPU baseline: the FP64 oracle on a bounded sample, host cores

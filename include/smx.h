@@ -35,6 +35,15 @@
  *                     the simplex exit (Sec. I).
  *     SMX_MAP_LINEAR  linear enumeration g: Z^1 -> Z^m (Sec. I): FP32 square /
  *                     cube root of the block index plus an exact integer fix-up.
+ *     SMX_MAP_LAMBDA_BELOW  the paper's "approach n from below" (Sec. III-A):
+ *                     nb split into its binary digits (largest first); per
+ *                     segment of m tiles, lambda over m (a power of two) for
+ *                     its diagonal part and the identity for the rest --
+ *                     2-simplex: the rectangle above the segment; 3-simplex:
+ *                     lambda2(m) x identity and identity x (2-simplex from
+ *                     below).  No filtered blocks in 2-D; in 3-D only those of
+ *                     the lambda3 parts.  Block order: segment by segment, each
+ *                     part in that order.
  *   The map changes only the schedule.  EDM outputs are bit-identical across
  *   maps; energies and gradients agree to rounding (atomic order).
  * - Statistics (d_stats, nullable): int64[4] =
@@ -63,7 +72,7 @@ typedef enum {
     SMX_EHIP = 4         /* a HIP call or kernel launch failed */
 } smx_status;
 
-typedef enum { SMX_MAP_LAMBDA = 0, SMX_MAP_BBOX = 1, SMX_MAP_LINEAR = 2 } smx_map;
+typedef enum { SMX_MAP_LAMBDA = 0, SMX_MAP_BBOX = 1, SMX_MAP_LINEAR = 2, SMX_MAP_LAMBDA_BELOW = 3 } smx_map;
 
 typedef enum {
     SMX_EDM_FP32_DIFF = 0,      /* sum_k (x_ik - x_jk)^2 in FP32 on the vector ALUs */
@@ -131,6 +140,19 @@ int smx_simplex_map2(int64_t n, int rho, int map, int strict, int32_t *d_tiles,
  * lambda2 grid over nb whose tile (X, Y) is mapped to (X, Y, Y). */
 int smx_simplex_map3(int64_t n, int rho, int map, int strict, int32_t *d_tiles,
                      int64_t *d_stats, void *d_ws, size_t ws_bytes, void *stream);
+
+/* Parallel space only (paper Sec. I and III: the cost of a map is the map plus
+ * the blocks it launches).  Launches the parallel space of `map` for m in
+ * {2, 3}, n elements per dimension and tile edge rho (power of two, <= 1024
+ * for m = 2, <= 64 for m = 3) with 256-thread blocks; each block that maps to
+ * a tile adds the number of simplex elements of that tile (le, or lt when
+ * strict != 0), obtained in closed form, and filtered blocks exit at once.
+ *   d_stats  int64[4]: [0] elements (= smx_volume(m, n, strict)), [1] 0,
+ *            [2] blocks that mapped to a tile, [3] blocks launched.
+ *   d_ws     smx_workspace_bytes(0, ...) bytes.
+ * n = 0 writes zeros. */
+int smx_simplex_count(int m, int64_t n, int rho, int map, int strict, int64_t *d_stats, void *d_ws,
+                      size_t ws_bytes, void *stream);
 
 /* Packed Euclidean distance matrix (paper Sec. I and II: the EDM is a
  * 2-simplex problem whose upper triangle suffices).

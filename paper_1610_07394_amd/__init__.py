@@ -16,7 +16,7 @@ import torch
 
 __all__ = [
     "MAPS", "PRECS", "SmxError", "Pot", "lib", "volume", "parallel_blocks", "map_tiles_host",
-    "workspace_bytes", "simplex_map2", "simplex_map3", "edm_packed", "triplet_energy",
+    "workspace_bytes", "simplex_map2", "simplex_map3", "simplex_count", "edm_packed", "triplet_energy",
     "triplet_energy_grad", "triplet_energy_backward", "TripletEnergy", "profile_enable",
     "profile_reset", "profile_read", "KERNELS",
 ]
@@ -76,6 +76,7 @@ def lib():
         L.smx_workspace_bytes.restype = _sz
         for name in ("smx_simplex_map2", "smx_simplex_map3"):
             getattr(L, name).argtypes = [_i64, _i32, _i32, _i32, _vp, _vp, _vp, _sz, _vp]
+        L.smx_simplex_count.argtypes = [_i32, _i64, _i32, _i32, _i32, _vp, _vp, _sz, _vp]
         L.smx_edm_packed.argtypes = [_vp, _i64, _i64, _i64, _i32, _i32, _vp, _vp, _sz, _vp, _vp]
         L.smx_triplet_energy.argtypes = [_vp, _i64, _i64, ctypes.POINTER(_Pot), _i32, _vp, _vp, _sz, _vp, _vp]
         L.smx_triplet_energy_grad.argtypes = [_vp, _i64, _i64, ctypes.POINTER(_Pot), _i32, _vp, _vp, _vp,
@@ -177,6 +178,16 @@ def simplex_map2(n: int, rho: int, map="lambda", strict=False, tiles=True, stats
 def simplex_map3(n: int, rho: int, map="lambda", strict=False, tiles=True, stats=True, device="cuda"):
     """Run the 3-simplex parallel space; returns (tiles int32 [G, 3] | None, stats int64 [4] | None)."""
     return _simplex_map(3, n, rho, map, strict, tiles, stats, device)
+
+
+def simplex_count(m: int, n: int, rho: int, map="lambda", strict=False, device="cuda"):
+    """Parallel space only: int64 [4] = elements (closed form per mapped tile),
+    0, mapped blocks, launched blocks."""
+    device = torch.device(device)
+    s = torch.zeros(4, dtype=torch.int64, device=device)
+    ws = _ws(workspace_bytes(0, n), device)
+    _check(lib().smx_simplex_count(m, n, rho, _map(map), int(strict), _ptr(s), _ptr(ws), ws.numel(), _stream()))
+    return s
 
 
 # ---------------------------------------------------------------- EDM

@@ -268,6 +268,23 @@ int smx_simplex_map3(int64_t n, int rho, int map, int strict, int32_t *d_tiles, 
     return map_dump(3, n, rho, map, strict, d_tiles, d_stats, d_ws, ws_bytes, stream);
 }
 
+int smx_simplex_count(int m, int64_t n, int rho, int map, int strict, int64_t *d_stats, void *d_ws,
+                      size_t ws_bytes, void *stream) {
+    int rc = check_common(m, n, rho, map, m == 2 ? 1024 : 64);
+    if (rc != SMX_OK) return rc;
+    if (d_stats == nullptr) return fail(SMX_EINVAL, "stats must not be NULL");
+    if (d_ws == nullptr || ws_bytes < kSlotBytes)
+        return fail(SMX_EINVAL, "a workspace of %zu bytes is required", kSlotBytes);
+    unsigned long long *slots = reinterpret_cast<unsigned long long *>(d_ws);
+    if ((rc = launch_fill_u64(reinterpret_cast<uint64_t *>(slots), kSlotBytes / 8, S(stream)))) return rc;
+    MapGeom g{};
+    if (n > 0) {
+        if (!make_geom(m, (n + rho - 1) / rho, map, g)) return SMX_EOVERFLOW;
+        if ((rc = launch_count(m, g, n, rho, map, strict, slots, S(stream)))) return rc;
+    }
+    return launch_stats_finalize(slots, g.G, d_stats, S(stream));
+}
+
 int smx_edm_packed(const float *d_X, int64_t n, int64_t d, int64_t ldx, int map, int prec, float *d_D,
                    void *d_ws, size_t ws_bytes, int64_t *d_stats, void *stream) {
     if (n < 0) return fail(SMX_EINVAL, "n must be >= 0");

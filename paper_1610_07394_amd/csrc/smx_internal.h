@@ -59,6 +59,8 @@ int launch_map2(const MapGeom &g, int64_t n, int rho, int map, int strict, int32
                 unsigned long long *slots, hipStream_t s);
 int launch_map3(const MapGeom &g, int64_t n, int rho, int map, int strict, int32_t *tiles,
                 unsigned long long *slots, hipStream_t s);
+int launch_count(int m, const MapGeom &g, int64_t n, int rho, int map, int strict,
+                 unsigned long long *slots, hipStream_t s);
 
 // FP32 difference form: 128 x 128 tiles (8 x 8 per thread) once there are
 // enough of them to fill the chip, 64 x 64 (4 x 4 per thread) below that.

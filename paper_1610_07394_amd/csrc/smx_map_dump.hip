@@ -109,6 +109,75 @@ __global__ __launch_bounds__(kMapThreads) void map3_kernel(MapGeom g, int64_t n,
     if (threadIdx.x == 0) stats_add(slots, lin, c, h);
 }
 
+// Element count of one tile in closed form: t = elements of a tile edge that
+// lie below n; a diagonal pair of tile coordinates holds a triangle, a
+// diagonal triple a tetrahedron.
+__device__ __forceinline__ uint64_t edge_len(int T, int rho, int64_t n) {
+    const int64_t r = n - int64_t(T) * rho;
+    return r <= 0 ? 0 : (r < rho ? uint64_t(r) : uint64_t(rho));
+}
+__device__ __forceinline__ uint64_t tri_cnt(uint64_t t, bool strict) {
+    return strict ? (t == 0 ? 0 : t * (t - 1) / 2) : t * (t + 1) / 2;
+}
+__device__ __forceinline__ uint64_t tet_cnt(uint64_t t, bool strict) {
+    return strict ? (t < 3 ? 0 : t * (t - 1) * (t - 2) / 6) : t * (t + 1) * (t + 2) / 6;
+}
+
+// Map-only parallel space: each mapped block adds its tile's element count
+// (one atomic from one lane); no per-element work, so the kernel time is the
+// map plus the cost of the blocks launched -- the quantity the paper's
+// parallel-space analysis is about.
+template <int MAP, bool STRICT>
+__global__ __launch_bounds__(kMapThreads) void count2_kernel(MapGeom g, int64_t n, int rho,
+                                                            unsigned long long *slots) {
+    uint64_t lin;
+    int X, Y;
+    if (!tile2_of<MAP, false>(g, lin, X, Y)) return;
+    if (threadIdx.x != 0) return;
+    const uint64_t a = edge_len(X, rho, n), c = edge_len(Y, rho, n);
+    const uint64_t cnt = X < Y ? a * c : tri_cnt(a, STRICT);
+    unsigned long long *s = slots + (lin % kSlots) * kSlotStride;
+    atomicAdd(s + 0, (unsigned long long)cnt);
+    atomicAdd(s + 2, 1ull);
+}
+
+template <int MAP, bool STRICT>
+__global__ __launch_bounds__(kMapThreads) void count3_kernel(MapGeom g, int64_t n, int rho,
+                                                            unsigned long long *slots) {
+    uint64_t lin;
+    int X, Y, Z;
+    if (!tile3_of<MAP, false>(g, lin, X, Y, Z)) return;
+    if (threadIdx.x != 0) return;
+    const uint64_t a = edge_len(X, rho, n), b = edge_len(Y, rho, n), c = edge_len(Z, rho, n);
+    uint64_t cnt;
+    if (X < Y && Y < Z) cnt = a * b * c;
+    else if (X == Y && Y < Z) cnt = tri_cnt(a, STRICT) * c;
+    else if (X < Y) cnt = a * tri_cnt(b, STRICT);
+    else cnt = tet_cnt(a, STRICT);
+    unsigned long long *s = slots + (lin % kSlots) * kSlotStride;
+    atomicAdd(s + 0, (unsigned long long)cnt);
+    atomicAdd(s + 2, 1ull);
+}
+
+int launch_count(int m, const MapGeom &g, int64_t n, int rho, int map, int strict,
+                 unsigned long long *slots, hipStream_t s) {
+    prof_begin(m == 2 ? K_MAP2 : K_MAP3, s);
+    map_switch(map, [&](auto M) {
+        constexpr int MAPK = decltype(M)::value;
+        if (m == 2) {
+            const dim3 grid = MAPK == MAP_BBOX ? dim3(g.nb, g.nb, 1) : grid_for(g.G, kMapThreads);
+            if (strict) hipLaunchKernelGGL((count2_kernel<MAPK, true>), grid, dim3(kMapThreads), 0, s, g, n, rho, slots);
+            else hipLaunchKernelGGL((count2_kernel<MAPK, false>), grid, dim3(kMapThreads), 0, s, g, n, rho, slots);
+        } else {
+            const dim3 grid = MAPK == MAP_BBOX ? dim3(g.nb, g.nb, g.nb) : grid_for(g.G, kMapThreads);
+            if (strict) hipLaunchKernelGGL((count3_kernel<MAPK, true>), grid, dim3(kMapThreads), 0, s, g, n, rho, slots);
+            else hipLaunchKernelGGL((count3_kernel<MAPK, false>), grid, dim3(kMapThreads), 0, s, g, n, rho, slots);
+        }
+    });
+    prof_end(m == 2 ? K_MAP2 : K_MAP3, s);
+    return check_launch("simplex_count");
+}
+
 template <int MAP>
 static void go_map2(const MapGeom &g, int64_t n, int rho, int lgrho, int strict, int32_t *tiles,
                     unsigned long long *slots, hipStream_t s) {

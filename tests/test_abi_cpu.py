@@ -42,7 +42,7 @@ def test_version_and_volume():
 
 @pytest.mark.parametrize("m,n,rho", [(2, 1024, 16), (2, 65536, 64), (2, 1000, 16), (3, 2048, 32),
                                      (3, 8192, 32), (3, 100, 8), (2, 1, 16), (3, 5, 1)])
-@pytest.mark.parametrize("kind", ["lambda", "bbox", "linear"])
+@pytest.mark.parametrize("kind", ["lambda", "bbox", "linear", "lambda_below"])
 def test_parallel_blocks_match_oracle(m, n, rho, kind):
     nb = (n + rho - 1) // rho
     if m == 3 and kind == "bbox" and nb > 64:
@@ -53,7 +53,7 @@ def test_parallel_blocks_match_oracle(m, n, rho, kind):
 
 
 @pytest.mark.parametrize("nb", [1, 2, 3, 4, 7, 8, 16, 33, 64, 100, 512, 1024, 4096])
-@pytest.mark.parametrize("kind", ["lambda", "bbox", "linear"])
+@pytest.mark.parametrize("kind", ["lambda", "bbox", "linear", "lambda_below"])
 def test_host_map2_equals_oracle(nb, kind):
     if kind == "bbox" and nb > 1024:
         pytest.skip("bbox dump of nb^2 blocks checked at smaller nb")
@@ -63,7 +63,7 @@ def test_host_map2_equals_oracle(nb, kind):
 
 
 @pytest.mark.parametrize("nb", [1, 2, 3, 4, 5, 8, 16, 31, 64, 128, 256])
-@pytest.mark.parametrize("kind", ["lambda", "bbox", "linear"])
+@pytest.mark.parametrize("kind", ["lambda", "bbox", "linear", "lambda_below"])
 def test_host_map3_equals_oracle(nb, kind):
     if kind == "bbox" and nb > 64:
         pytest.skip("bbox dump of nb^3 blocks checked at smaller nb")
@@ -106,6 +106,13 @@ def test_validation_errors_before_any_device_work():
     assert L.smx_simplex_map2(16, 16, 0, 0, null, ctypes.c_void_p(8), null, 0, null) == 1
     # n = 0 is a no-op
     assert L.smx_simplex_map2(0, 16, 0, 0, null, null, null, 0, null) == 0
+    # parallel-space count: bad m / rho / map, no stats, no workspace
+    assert L.smx_simplex_count(4, 16, 1, 0, 0, ctypes.c_void_p(256), ctypes.c_void_p(256), 1 << 20, null) == 1
+    assert L.smx_simplex_count(2, 16, 3, 0, 0, ctypes.c_void_p(256), ctypes.c_void_p(256), 1 << 20, null) == 1
+    assert L.smx_simplex_count(2, 16, 1, 9, 0, ctypes.c_void_p(256), ctypes.c_void_p(256), 1 << 20, null) == 1
+    assert L.smx_simplex_count(2, 16, 1, 0, 0, null, ctypes.c_void_p(256), 1 << 20, null) == 1
+    assert L.smx_simplex_count(3, 16, 1, 0, 0, ctypes.c_void_p(256), null, 0, null) == 1
+    assert b"workspace" in L.smx_last_error()
     # EDM argument checks
     assert L.smx_edm_packed(null, 10, 0, 3, 0, 0, null, null, 0, null, null) == 1
     assert L.smx_edm_packed(null, 10, 3, 2, 0, 0, null, null, 0, null, null) == 1

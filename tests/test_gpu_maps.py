@@ -15,7 +15,7 @@ from oracle import maps as omaps
 pytestmark = pytest.mark.gpu
 
 GOLD = os.path.join(os.path.dirname(__file__), "golden", "expected.json")
-KINDS = ["lambda", "bbox", "linear"]
+KINDS = ["lambda", "bbox", "linear", "lambda_below"]
 
 
 def _gold():
@@ -100,3 +100,16 @@ def test_lambda_block_counts_match_paper_ratios():
     main = smx.parallel_blocks(3, 8192, 32, "lambda") - nb * (nb + 1) // 2
     assert main == 3 * nb ** 3 // 16
     assert abs(main / ((nb ** 3 - nb) / 6) - 9 / 8) < 1e-4
+
+
+@pytest.mark.parametrize("m,n,rho", [(2, 1024, 16), (2, 1000, 16), (2, 65536, 16), (2, 33 * 64 + 5, 64),
+                                     (3, 8192, 8), (3, 1000, 8), (3, 33 * 32, 32), (3, 5, 1)])
+@pytest.mark.parametrize("kind", KINDS)
+@pytest.mark.parametrize("strict", [False, True])
+def test_count_kernel_closed_form(m, n, rho, kind, strict):
+    """Parallel space only: the per-tile closed-form counts add up to the volume."""
+    s = smx.simplex_count(m, n, rho, kind, strict).cpu().numpy()
+    nb = -(-n // rho)
+    assert int(s[0]) == oracle.simplex_volume(m, n, strict)
+    assert int(s[2]) == (nb * (nb + 1) // 2 if m == 2 else nb * (nb + 1) * (nb + 2) // 6)
+    assert int(s[3]) == smx.parallel_blocks(m, n, rho, kind)

@@ -52,14 +52,14 @@ def test_lambda3_golden_nb4():
     assert len(g) == t.shape[0]
 
 
-@pytest.mark.parametrize("kind", ["lambda", "bbox", "linear"])
+@pytest.mark.parametrize("kind", ["lambda", "bbox", "linear", "lambda_below"])
 @pytest.mark.parametrize("nb", [1, 2, 3, 4, 5, 7, 8, 12, 16, 33, 64, 100, 256])
 def test_map2_bijection(kind, nb):
     ok, msg = maps.check_bijection(maps.tiles(2, nb, kind), 2, nb)
     assert ok, msg
 
 
-@pytest.mark.parametrize("kind", ["lambda", "bbox", "linear"])
+@pytest.mark.parametrize("kind", ["lambda", "bbox", "linear", "lambda_below"])
 @pytest.mark.parametrize("nb", [1, 2, 3, 4, 5, 6, 8, 12, 16, 32])
 def test_map3_bijection(kind, nb):
     ok, msg = maps.check_bijection(maps.tiles(3, nb, kind), 3, nb)
@@ -216,3 +216,41 @@ def test_recursive_set_limits():
         a = v / comb(n - 1 + m - 1, m) - 1
         assert abs(float(a - lim)) < 1e-6
         assert Fraction(factorial(m), 2 ** m - 2) - 1 == lim
+
+
+# --------------------------------------------------------------------------
+# "Approach n from below" (Sec. III-A): n_1 = 2^floor(log2 n), then
+# n_i = 2^floor(log2(n - sum_{k<i} n_k)).
+@pytest.mark.parametrize("nb", [1, 2, 3, 5, 6, 7, 12, 13, 33, 100, 255, 1000])
+def test_below_segments_follow_paper_rule(nb):
+    segs = maps.segments(nb)
+    rest, off = nb, 0
+    for o, m in segs:
+        expect = 1
+        while expect * 2 <= rest:
+            expect *= 2
+        assert (o, m) == (off, expect)
+        off += m
+        rest -= m
+    assert rest == 0 and off == nb
+
+
+@pytest.mark.parametrize("nb", [1, 3, 5, 12, 13, 33, 100, 255])
+def test_below2_has_no_filtered_blocks(nb):
+    t = maps.below2_tiles(nb)
+    assert t.shape[0] == nb * (nb + 1) // 2 and (t >= 0).all()
+
+
+@pytest.mark.parametrize("nb", [3, 5, 12, 13, 33])
+def test_below3_block_count(nb):
+    """Blocks: per segment, lambda3 of m (3 m^3/16 + m(m+1)/2 blocks) plus the
+    two prisms m(m+1)/2 * r and m * r(r+1)/2, r = tiles above the segment."""
+    total = 0
+    for o, m in maps.segments(nb):
+        r = nb - o - m
+        l3 = (m // 2) * (m // 2) * (m // 2 + m // 4) + (1 if m == 1 else (m // 2) * (m + 1))
+        total += l3 + m * (m + 1) // 2 * r + m * r * (r + 1) // 2
+    assert maps.below3_tiles(nb).shape[0] == total
+    # far fewer blocks than "from above" just past a power of two
+    if nb == 33:
+        assert total < maps.lambda3_tiles(33).shape[0] / 5
