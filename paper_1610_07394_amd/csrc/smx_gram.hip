@@ -10,9 +10,9 @@
 //
 // Block: 256 threads (4 waves as 2 x 2), tile 128 x 128 of the packed upper
 // triangle, each wave 64 x 64 = 2 x 2 MFMA tiles of 32 x 32.  K advances in
-// chunks of 32 through LDS (row-major, row stride 40 bf16 = 80 bytes so the
-// 16-byte fragment reads of 16 consecutive rows hit distinct bank groups), with
-// the next chunk prefetched into registers while the matrix cores run.
+// chunks of 32 BF16 through two alternating LDS buffers filled directly from
+// global memory in MFMA fragment order (see the staging notes below), so the
+// loads of chunk s + 1 are in flight while the matrix cores run chunk s.
 #include "smx_device.h"
 #include "smx_internal.h"
 
@@ -22,7 +22,6 @@ typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
 typedef float f32x16_t __attribute__((ext_vector_type(16)));
 
 constexpr int kGramThreads = 256;
-constexpr int kGramLd = kGramK + 8;  // 40 bf16 per LDS row
 
 __device__ __forceinline__ uint16_t bf16_rne(float f) {
     uint32_t u = __float_as_uint(f);
