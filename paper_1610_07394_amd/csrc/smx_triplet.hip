@@ -6,31 +6,46 @@
 // s3 = |x_i - x_k|^2 (law of cosines: cos g = t / (2 r r)):
 //   E_t = nu (P - 3/8 T) P^(-5/2),   P = s1 s2 s3,   T = t1 t2 t3,
 //   t1 = s3 - s1 - s2,  t2 = s1 - s2 - s3,  t3 = s2 - s3 - s1.
+// The kernel evaluates the same quantity in symmetric-function form.  With
+// u = s1 + s2 + s3 and g = 4 s2 s3 - (s1 - s2 - s3)^2 (= 16 x squared triangle
+// area, symmetric in the three pairs), T = t1 t2 t3 = 8 P - u g, so
+//   P - 3/8 T = 3/8 u g - 2 P,
+// and its derivative with respect to one pair term s_p, together with
+// dP^(-5/2)/ds_p = -5/2 P^(-5/2) / s_p, gives
+//   dE_t/ds_p = 3/8 nu R (K - 4 u s_p - Q / s_p),
+//   R = P^(-5/2),  K = g + 2 u^2,  Q = 5/2 u g - 8 P,
+//   E_t = 1/4 nu R (Q - u g).
+// Per pair the kernel keeps s, -4 s and d^5 (d = 1/r), so R = d1^5 d2^5 d3^5
+// and the triplet loop has no square root, division or per-triplet power.
+// The loop accumulates s_p dE_t/ds_p = 3/8 nu R (s_p (K - 4 u s_p) - Q)
+// (K - 4 u s_1 as g - 2 u t2) and the sums are scaled by 1/s_p once per pair
+// after the loop.  E_t is homogeneous of
+// degree -9/2 in the pair terms, so (Euler) sum_p s_p dE_t/ds_p = -9/2 E_t:
+// the energy is read off the same sums, E_t = -(nu / 12) R sum_p x_p with
+// x_p = s_p (K - 4 u s_p) - Q.  About 24 FP32 operations per triplet give the
+// energy and all three weights.
 // The gradient never forms per-particle forces per triplet.  Because E depends
 // on positions only through the pair terms, dE/dx_a = sum_b 2 W_ab (x_a - x_b)
 // with W_ab = sum over triplets holding the pair {a, b} of dE_t/ds_ab.  So each
-// triplet only adds three scalars:
-//   dE_t/ds_p = nu (dP_p A' + dT_p B'),   A' = R - 5/2 N R / P,   B' = -3/8 R,
-//   R = P^(-5/2), N = P - 3/8 T, dP = (s2 s3, s1 s3, s1 s2),
-//   dT1 = 2 m2 - M, dT2 = 2 m3 - M, dT3 = 2 m1 - M,
-//   m1 = t2 t3, m2 = t1 t3, m3 = t1 t2, M = m1 + m2 + m3.
-// P^(-1/2) = d1 d2 d3 with d = 1/r per pair, so the triplet loop needs no
-// square root: R = (d1 d2 d3)^5 and 1/P = (d1 d2 d3)^2.
+// triplet only adds three scalars.
 //
 // Block: 256 threads own the 32^3 triplets of tile (X, Y, Z), X <= Y <= Z.
 //   1. positions of the three 32-particle tiles -> LDS;
-//   2. the 3 x 32 x 32 pair terms s and d -> LDS; d = 0 for a pair that is out
-//      of order (i >= j, j >= k, i >= k) or past n, which zeroes R for every
-//      triplet containing it -- the simplex mask costs nothing per triplet and
-//      diagonal tiles run the same code;
+//   2. the 3 x 32 x 32 pair terms s, -4 s, d^5 -> LDS; d^5 = 0 for a pair that
+//      is out of order (i >= j, j >= k, i >= k) or past n, which zeroes R for
+//      every triplet containing it -- the simplex mask costs nothing per
+//      triplet and diagonal tiles run the same code;
 //   3. each thread runs 4 i x 4 j x 8 k (wave kb owns k in [8 kb, 8 kb + 8));
-//      per k, the weights W_ik and W_jk are summed across lanes with DPP
-//      (quad_perm within a quad, row_ror 4 / 8 across a row's quads) and each
-//      entry is stored once into one of two half-wave planes; W_ij stays in
-//      registers and each wave stores its own slice after the loop.  LDS
-//      atomics cost far more than these shuffles on gfx950, and none remain;
-//   4. pair weights -> forces on the 96 particles (64 pair terms each, two
-//      threads per particle; the planes and slices are summed on read), FP64
+//      the (i, j) pair terms stay in registers for the whole loop; per k, the
+//      weights W_ik and W_jk are summed across lanes with DPP (quad_perm
+//      within a quad, row_ror 4 / 8 across a row's quads) and each entry is
+//      stored once into one of two half-wave planes; W_ij stays in registers
+//      and each wave stores its own slice after the loop.  LDS atomics cost
+//      far more than these shuffles on gfx950, and none remain;
+//   4. the planes and slices are summed into one plane per pair set, scaled
+//      by 1/s_p (0 outside the simplex), and each is also stored transposed,
+//      so every particle reads its weights along a row; pair weights -> forces on the 96 particles (one wave per tile,
+//      half a wave per pair set), x_a sum_b W_ab - sum_b W_ab x_b, FP64
 //      atomics into the gradient;
 //   5. energy: wave / block sums in FP64, one atomic into a spread slot.
 #include "smx_device.h"
@@ -70,14 +85,23 @@ __global__ __launch_bounds__(kTripThreads, 3) void at_kernel(MapGeom g, const fl
     if (!tile3_of<MAP, true>(g, lin, TX, TY, TZ)) return;
 
     constexpr int PS = kTripTile * kTripLd;
+    // LDS planes of PS floats.  Pair sets: ij (rows i, cols j), ki (rows k,
+    // cols i), kj (rows k, cols j).
+    //   GRAD:  0 s_ki, 1 s_kj, 2 m4_ki, 3 m4_kj, 4 d5_ki, 5 d5_kj (m4 = -4 s);
+    //          6..9: s_ij, d5_ij until every thread holds its (i, j) terms in
+    //          registers, then the per-k weight planes W_ik (6, 7) and W_jk
+    //          (8, 9), stored [k][i] and [k][j].  After the loop 2..5 take the
+    //          W_ij slices; then W_ij [i][j] -> 2, W_ik [k][i] -> 6,
+    //          W_jk [k][j] -> 8 and their transposes -> 3, 7, 9.
+    //   energy only: 0 s_ki, 1 s_kj, 2 s_ij, 3 d5_ij, 4 d5_ki, 5 d5_kj.
+    constexpr int NP = GRAD ? 10 : 6;
+    constexpr int S_KI = 0, S_KJ = 1, M4_KI = 2, M4_KJ = 3, D5_KI = 4, D5_KJ = 5;
+    constexpr int S_IJ = GRAD ? 6 : 2, D5_IJ = GRAD ? 7 : 3, W_IK = 6, W_JK = 8;
     __shared__ float4 Pos[3][kTripTile];
-    // SD[0..2]: pair terms s ([i][j], [k][i], [k][j]); SD[3..5]: d = 1/r of the same
-    // pairs.  After the triplet loop SD[0..3] hold the four per-wave slices of W_ij.
-    __shared__ __attribute__((aligned(16))) float SD[6][PS];
-    // per-k weights W_ik ([plane][k][i]) and W_jk ([plane][k][j]), two planes each
-    __shared__ __attribute__((aligned(16))) float WZ[GRAD ? 4 : 1][GRAD ? PS : 1];
+    __shared__ __attribute__((aligned(16))) float L[NP * PS];
     __shared__ double red[kTripThreads / kWave];
     __shared__ unsigned long long sred[2][kTripThreads / kWave];
+    auto plane = [&](int i) -> float * { return L + i * PS; };
 
     const int t = threadIdx.x;
     const int64_t base[3] = {int64_t(TX) * kTripTile, int64_t(TY) * kTripTile, int64_t(TZ) * kTripTile};
@@ -97,81 +121,106 @@ __global__ __launch_bounds__(kTripThreads, 3) void at_kernel(MapGeom g, const fl
 
     // pair terms: set 0 rows i (X) cols j (Y); set 1 rows k (Z) cols i (X);
     // set 2 rows k (Z) cols j (Y).  Valid iff the pair is in triplet order
-    // (i < j, i < k, j < k) and the larger index is < n.
-    for (int e = t; e < 3 * kTripTile * kTripTile; e += kTripThreads) {
-        const int set = e >> 10, r = (e >> 5) & 31, c = e & 31;
-        const int ta = set == 0 ? 0 : 2, tb = set == 2 ? 1 : (set == 0 ? 1 : 0);
-        const float4 pa = Pos[ta][r], pb = Pos[tb][c];
-        const float dx = pb.x - pa.x, dy = pb.y - pa.y, dz = pb.z - pa.z;
-        const float s = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dx * dx));
-        const int64_t ga = base[ta] + r, gb = base[tb] + c;
-        const bool valid = set == 0 ? (ga < gb && gb < n) : (gb < ga && ga < n);
-        SD[set][r * kTripLd + c] = s;
-        SD[3 + set][r * kTripLd + c] = valid ? __builtin_amdgcn_rsqf(s) : 0.f;
+    // (i < j, i < k, j < k) and the larger index is < n.  Thread t takes
+    // column t % 32 and rows t / 32 + 8 it of every set; indices fit 32 bits
+    // (n < 2^31, tile bases < n + 32).
+    {
+        const int c = t & 31, r0 = t >> 5;
+        const uint32_t un = uint32_t(n);
+        const uint32_t bt[3] = {uint32_t(base[0]), uint32_t(base[1]), uint32_t(base[2])};
+#pragma unroll
+        for (int set = 0; set < 3; ++set) {
+            const int ta = set == 0 ? 0 : 2, tb = set == 2 ? 1 : (set == 0 ? 1 : 0);
+            const float4 pb = Pos[tb][c];
+            const uint32_t gb = bt[tb] + uint32_t(c);
+#pragma unroll
+            for (int it = 0; it < 4; ++it) {
+                const int r = r0 + 8 * it;
+                const float4 pa = Pos[ta][r];
+                const float dx = pb.x - pa.x, dy = pb.y - pa.y, dz = pb.z - pa.z;
+                const float sv = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dx * dx));
+                const uint32_t ga = bt[ta] + uint32_t(r);
+                const bool valid = set == 0 ? (ga < gb && gb < un) : (gb < ga && ga < un);
+                const float d = valid ? __builtin_amdgcn_rsqf(sv) : 0.f;
+                const float rs = d * d;
+                const int o = r * kTripLd + c;
+                plane(set == 0 ? S_IJ : S_KI + set - 1)[o] = sv;
+                plane(set == 0 ? D5_IJ : D5_KI + set - 1)[o] = (rs * rs) * d;
+                if (GRAD && set != 0) plane(M4_KI + set - 1)[o] = -4.f * sv;
+            }
+        }
     }
     __syncthreads();
 
     // lane = 16 row + 4 q + e;  ib = 4 (row >> 1) + q,  jb = 4 (row & 1) + e;
     // the thread owns i in 4 ib + [0,4), j in 4 jb + [0,4), k in 8 kb + [0,8)
-    const int lane = t & 63, kb = t >> 6, row = lane >> 4, q = (lane >> 2) & 3, el = lane & 3;
+    const int lane = t & 63, row = lane >> 4, q = (lane >> 2) & 3, el = lane & 3;
+    const int kb = __builtin_amdgcn_readfirstlane(t >> 6);  // wave index
     const int ib = 4 * (row >> 1) + q, jb = 4 * (row & 1) + el;
-    float s1[4][4], d1[4][4], w1[4][4];
+    float s1[4][4], f1[4][4], w1[4][4];
 #pragma unroll
     for (int a = 0; a < 4; ++a) {
-        const float4 sv = *reinterpret_cast<const float4 *>(&SD[0][(4 * ib + a) * kTripLd + 4 * jb]);
-        const float4 dv = *reinterpret_cast<const float4 *>(&SD[3][(4 * ib + a) * kTripLd + 4 * jb]);
+        const int o = (4 * ib + a) * kTripLd + 4 * jb;
+        const float4 sv = *reinterpret_cast<const float4 *>(plane(S_IJ) + o);
+        const float4 fv = *reinterpret_cast<const float4 *>(plane(D5_IJ) + o);
         s1[a][0] = sv.x; s1[a][1] = sv.y; s1[a][2] = sv.z; s1[a][3] = sv.w;
-        d1[a][0] = dv.x; d1[a][1] = dv.y; d1[a][2] = dv.z; d1[a][3] = dv.w;
+        f1[a][0] = fv.x; f1[a][1] = fv.y; f1[a][2] = fv.z; f1[a][3] = fv.w;
 #pragma unroll
         for (int b = 0; b < 4; ++b) w1[a][b] = 0.f;
     }
+    // the (i, j) planes become the per-k weight planes
+    if (GRAD) __syncthreads();
     float e = 0.f;
     unsigned long long cnt = 0, cs = 0;
 
 #pragma unroll 1
     for (int r = 0; r < 8; ++r) {
         const int k = 8 * kb + r;
-        const float4 s3v = *reinterpret_cast<const float4 *>(&SD[1][k * kTripLd + 4 * ib]);
-        const float4 d3v = *reinterpret_cast<const float4 *>(&SD[4][k * kTripLd + 4 * ib]);
-        const float4 s2v = *reinterpret_cast<const float4 *>(&SD[2][k * kTripLd + 4 * jb]);
-        const float4 d2v = *reinterpret_cast<const float4 *>(&SD[5][k * kTripLd + 4 * jb]);
-        const float s3a[4] = {s3v.x, s3v.y, s3v.z, s3v.w}, d3a[4] = {d3v.x, d3v.y, d3v.z, d3v.w};
-        const float s2a[4] = {s2v.x, s2v.y, s2v.z, s2v.w}, d2a[4] = {d2v.x, d2v.y, d2v.z, d2v.w};
+        const int oi = k * kTripLd + 4 * ib, oj = k * kTripLd + 4 * jb;
+        const float4 s3v = *reinterpret_cast<const float4 *>(plane(S_KI) + oi);
+        const float4 f3v = *reinterpret_cast<const float4 *>(plane(D5_KI) + oi);
+        const float4 s2v = *reinterpret_cast<const float4 *>(plane(S_KJ) + oj);
+        const float4 f2v = *reinterpret_cast<const float4 *>(plane(D5_KJ) + oj);
+        const float s3a[4] = {s3v.x, s3v.y, s3v.z, s3v.w}, f3a[4] = {f3v.x, f3v.y, f3v.z, f3v.w};
+        const float s2a[4] = {s2v.x, s2v.y, s2v.z, s2v.w}, f2a[4] = {f2v.x, f2v.y, f2v.z, f2v.w};
+        float m3a[4], m2a[4];  // -4 s
+        if (GRAD) {
+            const float4 m3v = *reinterpret_cast<const float4 *>(plane(M4_KI) + oi);
+            const float4 m2v = *reinterpret_cast<const float4 *>(plane(M4_KJ) + oj);
+            m3a[0] = m3v.x; m3a[1] = m3v.y; m3a[2] = m3v.z; m3a[3] = m3v.w;
+            m2a[0] = m2v.x; m2a[1] = m2v.y; m2a[2] = m2v.z; m2a[3] = m2v.w;
+        } else {
+#pragma unroll
+            for (int b = 0; b < 4; ++b) m2a[b] = -4.f * s2a[b];
+        }
         float w2[4] = {0.f, 0.f, 0.f, 0.f}, w3[4] = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int a = 0; a < 4; ++a)
 #pragma unroll
             for (int b = 0; b < 4; ++b) {
                 const float sa = s1[a][b], sb = s2a[b], sc = s3a[a];
-                const float q23 = sb * sc;
-                const float P = sa * q23;
-                const float u = sa + sb + sc;
-                const float t1 = __builtin_fmaf(2.f, sc, -u);
-                const float t2 = __builtin_fmaf(2.f, sa, -u);
-                const float t3 = __builtin_fmaf(2.f, sb, -u);
-                const float Dd = d1[a][b] * (d2a[b] * d3a[a]);
-                const float D2 = Dd * Dd;
-                const float R = (D2 * D2) * Dd;
+                const float v = sb + sc;
+                const float t2n = v - sa;                   // -t2
+                const float u = sa + v;
+                const float q4 = -(m2a[b] * sc);            // 4 s2 s3
+                const float gg = __builtin_fmaf(-t2n, t2n, q4);  // g
+                const float y = u * gg;
+                const float P4 = sa * q4;                   // 4 P
+                const float R = f1[a][b] * (f2a[b] * f3a[a]);
                 if (!GRAD) {
-                    const float T = t1 * t2 * t3;
-                    const float N = __builtin_fmaf(-0.375f, T, P);
-                    e = __builtin_fmaf(N, R, e);
+                    // 4 (P - 3/8 T) = 3/2 u g - 8 P
+                    e = __builtin_fmaf(__builtin_fmaf(1.5f, y, -2.f * P4), R, e);
                 } else {
-                    const float m1 = t2 * t3, m2 = t1 * t3, m3 = t1 * t2;
-                    const float T = t1 * m1;
-                    const float N = __builtin_fmaf(-0.375f, T, P);
-                    const float NR = N * R;
-                    e += NR;
-                    const float A = __builtin_fmaf(-2.5f * NR, D2, R);
-                    const float B = -0.375f * R;
-                    const float M = m1 + m2 + m3;
-                    const float dT1 = __builtin_fmaf(2.f, m2, -M);
-                    const float dT2 = __builtin_fmaf(2.f, m3, -M);
-                    const float dT3 = __builtin_fmaf(2.f, m1, -M);
-                    const float q13 = sa * sc, q12 = sa * sb;
-                    w1[a][b] = __builtin_fmaf(q23, A, __builtin_fmaf(dT1, B, w1[a][b]));
-                    w2[b] = __builtin_fmaf(q13, A, __builtin_fmaf(dT2, B, w2[b]));
-                    w3[a] = __builtin_fmaf(q12, A, __builtin_fmaf(dT3, B, w3[a]));
+                    const float nQ = __builtin_fmaf(2.f, P4, -2.5f * y);  // -Q
+                    const float tu = u + u;
+                    const float K = __builtin_fmaf(tu, u, gg);
+                    // s_p (K - 4 u s_p) - Q;  K - 4 u s_1 = g - 2 u t2
+                    const float x1 = __builtin_fmaf(sa, __builtin_fmaf(tu, t2n, gg), nQ);
+                    const float x2 = __builtin_fmaf(sb, __builtin_fmaf(u, m2a[b], K), nQ);
+                    const float x3 = __builtin_fmaf(sc, __builtin_fmaf(u, m3a[a], K), nQ);
+                    w1[a][b] = __builtin_fmaf(R, x1, w1[a][b]);
+                    w2[b] = __builtin_fmaf(R, x2, w2[b]);
+                    w3[a] = __builtin_fmaf(R, x3, w3[a]);
                 }
                 if (STATS) {
                     const int64_t gi = base[0] + 4 * ib + a, gj = base[1] + 4 * jb + b, gk = base[2] + k;
@@ -182,24 +231,34 @@ __global__ __launch_bounds__(kTripThreads, 3) void at_kernel(MapGeom g, const fl
                 }
             }
         if (GRAD) {
+            // energy (Euler): the sums of R x_p over this thread's triplets
+            e += ((w2[0] + w2[1]) + (w2[2] + w2[3])) + ((w3[0] + w3[1]) + (w3[2] + w3[3]));
             // W_ik: sum the lane's partials over the quad (jb low bits); lane el
             // stores i = 4 ib + el into plane (row & 1).  W_jk: sum over the
             // row's quads (ib low bits); lane q stores j = 4 jb + q into plane
-            // (row >> 1).  Each entry has exactly one writer: no atomics.
+            // (row >> 1).  Each entry has exactly one writer: no atomics.  The
+            // sums carry a factor s_p, removed after the loop.
 #pragma unroll
             for (int a = 0; a < 4; ++a) w3[a] = quad_allsum(w3[a]);
 #pragma unroll
             for (int b = 0; b < 4; ++b) w2[b] = rowquads_allsum(w2[b]);
             const float v3 = el == 0 ? w3[0] : (el == 1 ? w3[1] : (el == 2 ? w3[2] : w3[3]));
             const float v2 = q == 0 ? w2[0] : (q == 1 ? w2[1] : (q == 2 ? w2[2] : w2[3]));
-            WZ[row & 1][k * kTripLd + 4 * ib + el] = v3;
-            WZ[2 + (row >> 1)][k * kTripLd + 4 * jb + q] = v2;
+            plane(W_IK + (row & 1))[oi + el] = v3;
+            plane(W_JK + (row >> 1))[oj + q] = v2;
         }
     }
 
-    // energy of the block, FP64 from the per-thread FP32 partials
+    // energy of the block, FP64 from the per-thread FP32 partials: sums of
+    // 4 (P - 3/8 T) R (energy only) or of R (x_1 + x_2 + x_3) = -12 (P - 3/8 T) R
+    if (GRAD) {
+#pragma unroll
+        for (int a = 0; a < 4; ++a) e += (w1[a][0] + w1[a][1]) + (w1[a][2] + w1[a][3]);
+    }
     const double eb = block_sum<double, kTripThreads>(double(e), red);
-    if (t == 0) atomicAdd(eslots + (lin % kSlots) * kSlotStride + 0, eb * double(nu));
+    if (t == 0)
+        atomicAdd(eslots + (lin % kSlots) * kSlotStride + 0,
+                  eb * (GRAD ? -double(nu) / 12.0 : 0.25 * double(nu)));
     if (STATS) {
         const unsigned long long c = block_sum<unsigned long long, kTripThreads>(cnt, sred[0]);
         const unsigned long long h = block_sum<unsigned long long, kTripThreads>(cs, sred[1]);
@@ -207,52 +266,73 @@ __global__ __launch_bounds__(kTripThreads, 3) void at_kernel(MapGeom g, const fl
     }
 
     if (GRAD) {
-        // every wave is past the triplet loop (block_sum synchronised): the pair
-        // terms are dead, so SD[kb] takes this wave's slice of W_ij
+        // every wave is past the triplet loop (block_sum synchronised): the
+        // -4 s and d^5 planes (2..5) are dead, so plane 2 + kb takes this
+        // wave's slice of W_ij (its sums carry s_ij: divide, 0 outside the
+        // simplex)
 #pragma unroll
-        for (int a = 0; a < 4; ++a)
-            *reinterpret_cast<float4 *>(&SD[kb][(4 * ib + a) * kTripLd + 4 * jb]) =
+        for (int a = 0; a < 4; ++a) {
+#pragma unroll
+            for (int b = 0; b < 4; ++b)
+                w1[a][b] = f1[a][b] != 0.f ? w1[a][b] * __builtin_amdgcn_rcpf(s1[a][b]) : 0.f;
+            *reinterpret_cast<float4 *>(plane(2 + kb) + (4 * ib + a) * kTripLd + 4 * jb) =
                 make_float4(w1[a][0], w1[a][1], w1[a][2], w1[a][3]);
+        }
         __syncthreads();
-        // particle p = t / 2 of the 96 (tile = p / 32), half h = t % 2:
-        //   X (i): h0 sum_j W_ij (x_i - x_j),  h1 sum_k W_ik (x_i - x_k)
-        //   Y (j): h0 sum_i W_ij (x_j - x_i),  h1 sum_k W_jk (x_j - x_k)
-        //   Z (k): h0 sum_i W_ik (x_k - x_i),  h1 sum_j W_jk (x_k - x_j)
-        if (t < 2 * 3 * kTripTile) {
-            const int p = t >> 1, h = t & 1, tile = p >> 5, a = p & 31;
-            const float4 me = Pos[tile][a];
-            float gx = 0.f, gy = 0.f, gz = 0.f;
-            int other;
-            if (tile == 0) other = h == 0 ? 1 : 2;
-            else if (tile == 1) other = h == 0 ? 0 : 2;
-            else other = h == 0 ? 0 : 1;
-#pragma unroll 4
-            for (int b = 0; b < kTripTile; ++b) {
-                float wgt;
-                if (tile == 0 && h == 0) {
-                    const int o = a * kTripLd + b;
-                    wgt = (SD[0][o] + SD[1][o]) + (SD[2][o] + SD[3][o]);
-                } else if (tile == 1 && h == 0) {
-                    const int o = b * kTripLd + a;
-                    wgt = (SD[0][o] + SD[1][o]) + (SD[2][o] + SD[3][o]);
-                } else if ((tile == 0 && h == 1) || (tile == 2 && h == 0)) {
-                    const int o = tile == 0 ? b * kTripLd + a : a * kTripLd + b;  // W_ik stored [k][i]
-                    wgt = WZ[0][o] + WZ[1][o];
-                } else {
-                    const int o = tile == 1 ? b * kTripLd + a : a * kTripLd + b;  // W_jk stored [k][j]
-                    wgt = WZ[2][o] + WZ[3][o];
+        // one plane per pair set: W_ij -> plane 2, W_ik -> 6, W_jk -> 8 (in
+        // place), the last two divided by s (a pair outside the simplex has
+        // zero sums; s = 0 only for such pairs)
+        for (int o = t; o < kTripTile * kTripTile; o += kTripThreads) {
+            const int x = (o >> 5) * kTripLd + (o & 31);
+            plane(2)[x] = (plane(2)[x] + plane(3)[x]) + (plane(4)[x] + plane(5)[x]);
+            const float ski = plane(S_KI)[x], skj = plane(S_KJ)[x];
+            plane(W_IK)[x] = ski > 0.f ? (plane(W_IK)[x] + plane(W_IK + 1)[x]) * __builtin_amdgcn_rcpf(ski) : 0.f;
+            plane(W_JK)[x] = skj > 0.f ? (plane(W_JK)[x] + plane(W_JK + 1)[x]) * __builtin_amdgcn_rcpf(skj) : 0.f;
+        }
+        __syncthreads();
+        // transposes: W_ji [j][i] -> 3, W_ik [i][k] -> 7, W_jk [j][k] -> 9
+        for (int o = t; o < kTripTile * kTripTile; o += kTripThreads) {
+            const int r = o >> 5, c = o & 31, x = r * kTripLd + c, xt = c * kTripLd + r;
+            plane(3)[xt] = plane(2)[x];
+            plane(W_IK + 1)[xt] = plane(W_IK)[x];
+            plane(W_JK + 1)[xt] = plane(W_JK)[x];
+        }
+        __syncthreads();
+        // wave T < 3 takes tile T; lane = 32 h + a: particle a, pair set h.
+        //   X (i): h0 W_ij [i][j] (plane 2) with j,  h1 W_ik [i][k] (7) with k
+        //   Y (j): h0 W_ji [j][i] (3) with i,        h1 W_jk [j][k] (9) with k
+        //   Z (k): h0 W_ki [k][i] (6) with i,        h1 W_kj [k][j] (8) with j
+        // dE/dx_a = 2 nu sum_b W_ab (x_a - x_b) = 2 nu (x_a sum_b W_ab - sum_b W_ab x_b)
+        if (kb < 3) {
+            const int tile = kb, a = lane & 31, h = lane >> 5;
+            const int pl = tile == 0 ? (h == 0 ? 2 : W_IK + 1)
+                                     : (tile == 1 ? (h == 0 ? 3 : W_JK + 1) : (h == 0 ? W_IK : W_JK));
+            const int other = tile == 0 ? 1 + h : (tile == 1 ? 2 * h : h);
+            const float *W = plane(pl) + a * kTripLd;
+            float ws = 0.f, wx = 0.f, wy = 0.f, wz = 0.f;
+#pragma unroll 2
+            for (int b = 0; b < kTripTile; b += 4) {
+                const float4 w4 = *reinterpret_cast<const float4 *>(W + b);
+                const float wv[4] = {w4.x, w4.y, w4.z, w4.w};
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    const float4 ot = Pos[other][b + c];
+                    ws += wv[c];
+                    wx = __builtin_fmaf(wv[c], ot.x, wx);
+                    wy = __builtin_fmaf(wv[c], ot.y, wy);
+                    wz = __builtin_fmaf(wv[c], ot.z, wz);
                 }
-                const float4 ot = Pos[other][b];
-                gx = __builtin_fmaf(wgt, me.x - ot.x, gx);
-                gy = __builtin_fmaf(wgt, me.y - ot.y, gy);
-                gz = __builtin_fmaf(wgt, me.z - ot.z, gz);
             }
-            gx += __shfl_xor(gx, 1, kWave);
-            gy += __shfl_xor(gy, 1, kWave);
-            gz += __shfl_xor(gz, 1, kWave);
+            const float4 me = Pos[tile][a];
+            float gx = __builtin_fmaf(me.x, ws, -wx), gy = __builtin_fmaf(me.y, ws, -wy),
+                  gz = __builtin_fmaf(me.z, ws, -wz);
+            gx += __shfl_xor(gx, 32, kWave);
+            gy += __shfl_xor(gy, 32, kWave);
+            gz += __shfl_xor(gz, 32, kWave);
             const int64_t gp = base[tile] + a;
             if (h == 0 && gp < n) {
-                const double sc = 2.0 * double(nu);
+                // W is 3/8 of the accumulated sums
+                const double sc = 0.75 * double(nu);
                 atomicAdd(G64 + 3 * gp + 0, sc * double(gx));
                 atomicAdd(G64 + 3 * gp + 1, sc * double(gy));
                 atomicAdd(G64 + 3 * gp + 2, sc * double(gz));
