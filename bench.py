@@ -153,6 +153,23 @@ def main():
             "elements_per_s": e / (t + kavg["gram_prep"] / 1e3),
             "mfma_tflops": 3 * 2 * D_GRAM * e / t / 1e12, "mfma_frac": 3 * 2 * D_GRAM * e / t / PEAK_BF16,
             "hbm_gbs": 4 * e / t / 1e9, "hbm_frac": 4 * e / t / PEAK_HBM}
+    if "gram" in only:
+        # the plain BF16 Gram form on the same input: bound by the 4-byte output stores
+        smx.edm_packed(X3, "lambda", "bf16", out=D3, ws=ws3)
+        torch.cuda.synchronize()
+        smx.profile_enable(True)
+        smx.profile_reset()
+        for _ in range(args.steps):
+            smx.edm_packed(X3, "lambda", "bf16", out=D3, ws=ws3)
+        ms, c = smx.profile_read("edm_gram")
+        smx.profile_enable(False)
+        t = ms / c / 1e3
+        e = elements["gram"]
+        byts = 4 * e + 2 * N_GRAM * D_GRAM * 2  # packed FP32 output + the BF16 operand once
+        comps["edm_bf16_n32768_d512"] = {
+            "elements": e, "kernel_ms": ms / c, "elements_per_s": e / t,
+            "mfma_tflops": 2 * D_GRAM * e / t / 1e12, "mfma_frac": 2 * D_GRAM * e / t / PEAK_BF16,
+            "hbm_gbs": byts / t / 1e9, "hbm_frac": byts / t / PEAK_HBM}
     if "at" in only:
         t = kavg["triplet_grad"] / 1e3
         tri = math.comb(N_AT, 3)

@@ -163,8 +163,11 @@ int smx_simplex_count(int m, int64_t n, int rho, int map, int strict, int64_t *d
  *   prec  smx_edm_prec.  Gram variants round X to BF16 with round-to-nearest-even
  *         (hi = bf16(x), lo = bf16(x - hi)), accumulate in FP32, add FP32 norms
  *         |x|^2, clamp the result at 0.
- *   d_ws  smx_workspace_bytes(1, n, d, prec, map) bytes (BF16 copies and norms
- *         for the Gram variants, statistics slots), or NULL when that is 0.
+ *   d_ws  smx_workspace_bytes(1, n, d, prec, map) bytes, or NULL when that is 0:
+ *         statistics slots and, for the Gram variants, FP32 norms and the BF16
+ *         hi (and lo) copies of X, rows padded to a multiple of 32 and columns
+ *         to a multiple of 32, stored in the matrix-core operand order (1 KB
+ *         per 32-row x 16-column block).  Its contents are scratch.
  *   d_stats nullable; counts pairs le. */
 int smx_edm_packed(const float *d_X, int64_t n, int64_t d, int64_t ldx, int map, int prec,
                    float *d_D, void *d_ws, size_t ws_bytes, int64_t *d_stats, void *stream);

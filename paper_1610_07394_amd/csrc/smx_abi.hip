@@ -137,10 +137,11 @@ static EdmWs edm_ws(int64_t n, int64_t d, int prec) {
     size_t off = kSlotBytes;
     if (prec != SMX_EDM_FP32_DIFF) {
         const int64_t dpad = (d + kGramK - 1) / kGramK * kGramK;
+        const int64_t npad = gram_rows(n);
         w.hi = off;
-        off = align256(off + size_t(n) * size_t(dpad) * 2);
+        off = align256(off + size_t(npad) * size_t(dpad) * 2);
         w.lo = off;
-        if (prec == SMX_EDM_SPLITBF16_GRAM) off = align256(off + size_t(n) * size_t(dpad) * 2);
+        if (prec == SMX_EDM_SPLITBF16_GRAM) off = align256(off + size_t(npad) * size_t(dpad) * 2);
         w.norms = off;
         off = align256(off + size_t(n) * 4);
     }
@@ -299,7 +300,7 @@ int smx_edm_packed(const float *d_X, int64_t n, int64_t d, int64_t ldx, int map,
     const bool need_ws = prec != SMX_EDM_FP32_DIFF || d_stats != nullptr;
     if (need_ws && (d_ws == nullptr || ws_bytes < w.total))
         return fail(SMX_EINVAL, "workspace of %zu bytes required (got %zu)", w.total, ws_bytes);
-    const int tile = prec == SMX_EDM_FP32_DIFF ? edm_diff_tile(n) : kGramTile;
+    const int tile = prec == SMX_EDM_FP32_DIFF ? edm_diff_tile(n) : gram_tile(n);
     MapGeom g;
     if (!make_geom(2, (n + tile - 1) / tile, map, g)) return SMX_EOVERFLOW;
     char *ws = reinterpret_cast<char *>(d_ws);
@@ -316,7 +317,7 @@ int smx_edm_packed(const float *d_X, int64_t n, int64_t d, int64_t ldx, int map,
         uint16_t *lo = reinterpret_cast<uint16_t *>(ws + w.lo);
         float *norms = reinterpret_cast<float *>(ws + w.norms);
         rc = launch_gram_prep(d_X, n, d, ldx, dpad, hi, lo, norms, split, S(stream));
-        if (rc == SMX_OK) rc = launch_edm_gram(g, hi, lo, norms, n, dpad, split, d_D, slots, S(stream));
+        if (rc == SMX_OK) rc = launch_edm_gram(g, tile, hi, lo, norms, n, dpad, split, d_D, slots, S(stream));
     }
     if (rc) return rc;
     if (slots) return launch_stats_finalize(slots, g.G, d_stats, S(stream));

@@ -125,11 +125,14 @@ __device__ __forceinline__ uint64_t tet_cnt(uint64_t t, bool strict) {
 
 // Map-only parallel space: each mapped block adds its tile's element count
 // (one atomic from one lane); no per-element work, so the kernel time is the
-// map plus the cost of the blocks launched -- the quantity the paper's
-// parallel-space analysis is about.
+// cost of the blocks launched plus one map evaluation per block -- the
+// quantity the paper's parallel-space analysis is about.  The block keeps the
+// 256 threads of the other kernels, but only its first wave evaluates the map
+// (the others have no element work here and leave at once, for every map).
 template <int MAP, bool STRICT>
 __global__ __launch_bounds__(kMapThreads) void count2_kernel(MapGeom g, int64_t n, int rho,
                                                             unsigned long long *slots) {
+    if (threadIdx.x >= kWave) return;
     uint64_t lin;
     int X, Y;
     if (!tile2_of<MAP, false>(g, lin, X, Y)) return;
@@ -144,6 +147,7 @@ __global__ __launch_bounds__(kMapThreads) void count2_kernel(MapGeom g, int64_t 
 template <int MAP, bool STRICT>
 __global__ __launch_bounds__(kMapThreads) void count3_kernel(MapGeom g, int64_t n, int rho,
                                                             unsigned long long *slots) {
+    if (threadIdx.x >= kWave) return;
     uint64_t lin;
     int X, Y, Z;
     if (!tile3_of<MAP, false>(g, lin, X, Y, Z)) return;

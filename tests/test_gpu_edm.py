@@ -162,7 +162,7 @@ def test_edm_full_size_gram(prec):
     torch.cuda.synchronize()
     assert torch.equal(D, Db)
     del Db
-    rows = sorted({0, 127, 128, 16383, n - 129, n - 128, n - 1,
+    rows = sorted({0, 127, 128, 255, 256, 16383, n - 257, n - 256, n - 129, n - 128, n - 1,
                    *np.random.default_rng(2).integers(0, n, 5).tolist()})
     nrm = (X.astype(np.float64) ** 2).sum(1)
     worst = 0.0
@@ -178,4 +178,30 @@ def test_edm_full_size_gram(prec):
         if e.size:
             worst = max(worst, float(e.max()))
     print(f"  {prec}: sampled max error {worst:.3e}")
+    assert worst <= TOL[prec]
+
+
+@pytest.mark.parametrize("prec", ["bf16", "split_bf16"])
+def test_edm_gram_large_tile_ragged(prec):
+    """n = 16484 (256-element Gram tiles, the last one ragged), d = 40 (K padded
+    to 64): all maps bit-identical; sampled rows at tile edges against the
+    oracle."""
+    n, d = 16484, 40
+    X = np.random.default_rng(11).standard_normal((n, d)).astype(np.float32)
+    Xt = torch.from_numpy(X).cuda()
+    D = smx.edm_packed(Xt, "lambda", prec)
+    for kind in KINDS[1:]:
+        assert torch.equal(D, smx.edm_packed(Xt, kind, prec)), kind
+    torch.cuda.synchronize()
+    rows = [0, 1, 255, 256, 511, 8191, 8192, 16383, 16384, n - 2, n - 1]
+    nrm = (X.astype(np.float64) ** 2).sum(1)
+    worst = 0.0
+    for i in rows:
+        a = int(i * n - i * (i - 1) // 2)
+        got = D[a:a + n - i].cpu().numpy().astype(np.float64)
+        ref = oracle.edm_rows(X, i, i + 1)
+        assert got[0] == 0.0 and (got >= 0).all()
+        if got.size > 1:
+            worst = max(worst, float((np.abs(got[1:] - ref[1:]) / (nrm[i] + nrm[i + 1:])).max()))
+    print(f"  {prec}: max error {worst:.3e}")
     assert worst <= TOL[prec]
