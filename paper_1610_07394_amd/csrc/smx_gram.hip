@@ -8,9 +8,8 @@
 // hi lo^T + lo hi^T, dropping lo lo^T (relative size 2^-16).  D is clamped
 // at 0 and the diagonal is set to exactly 0 (the Gram form cancels there).
 //
-// Block: 256 threads (4 waves as 2 x 2), tile T x T of the packed upper
-// triangle (T = 256 for n >= 16384, else 128), each wave T/2 x T/2 in MFMA
-// tiles of 32 x 32.  K advances in
+// Block: 256 threads (4 waves as 2 x 2), tile 128 x 128 of the packed upper
+// triangle, each wave 64 x 64 in MFMA tiles of 32 x 32.  K advances in
 // chunks of 32 BF16 through two alternating LDS buffers filled directly from
 // global memory in MFMA fragment order (see the staging notes below), so the
 // loads of chunk s + 1 are in flight while the matrix cores run chunk s.
@@ -92,41 +91,86 @@ int launch_gram_prep(const float *X, int64_t n, int64_t d, int64_t ldx, int64_t 
 // Staging.  Every MFMA operand fragment travels from global memory straight
 // into LDS with global_load_lds_dwordx4: one wave load moves one contiguous
 // 1 KB block of the fragment-ordered operand, lane s writing the 16 bytes it
-// later reads back as its operand.  Block (mb, ks) of a T-row panel chunk
-// holds rows mb*32 + (s & 31), k = ks*16 + 8*(s >> 5) .. +7, so an operand
-// read is base + 16*lane (no bank conflicts) and staging costs no VGPRs.  Two LDS buffers alternate: a wave
-// reads the fragments of chunk s, issues the loads of chunk s + 1 into the
-// other buffer, then runs the MFMAs of chunk s while those loads are in flight.
+// later reads back as its operand (rows mb*32 + (s & 31), k = 8*(s >> 5) .. +7
+// of one 16-wide k step), so an operand read is base + 16*lane (no bank
+// conflicts) and staging costs no VGPRs.
 //
-// WT = wave tile (64 or 128): the block tile is T = 2 WT, each wave owns
-// WT / 32 x WT / 32 MFMA tiles.  T = 256 halves the operand bytes per flop
-// (split BF16: 4 operand arrays x 16 KB per chunk, 128 KB of LDS, one block
-// per CU with 256 accumulator registers per lane).
+// Pipeline.  One stage = one 16-wide k step of both panels.  A ring of S
+// stages keeps S - 1 steps of loads in flight: at step s a wave waits until
+// only the loads of steps s+1 .. s+S-2 are outstanding (loads complete in
+// issue order), the block synchronises, the loads of step s+S-1 go into the
+// slot step s-1 used, and the MFMAs of step s run.
+//
+// WT = wave tile: the block tile is T = 2 WT, each wave owns WT / 32 x WT / 32
+// MFMA tiles.  T = 128 (WT = 64): 240 registers per lane and at most 64 KB of
+// LDS, so two blocks share a CU and one block's store-heavy epilogue overlaps
+// the other's MFMAs; measured on MI355X this beats T = 256 at one block per
+// CU, whose halved operand traffic does not bound the kernel.
 template <bool SPLIT, int WT>
 struct GramCfg {
-    static constexpr int NARR = SPLIT ? 4 : 2;  // A_hi, B_hi, (A_lo, B_lo)
-    static constexpr int T = 2 * WT;            // block tile edge
-    static constexpr int MT = WT / 32;          // MFMA tiles per wave edge
-    static constexpr int BLK = T / 32 * 2;      // 1 KB fragment blocks per array per chunk
+    static constexpr int NARR = SPLIT ? 4 : 2;     // A_hi, B_hi, (A_lo, B_lo)
+    static constexpr int T = 2 * WT;               // block tile edge
+    static constexpr int MT = WT / 32;             // MFMA tiles per wave edge
+    static constexpr int RB = T / 32;              // 32-row blocks per panel
+    static constexpr int STAGE = NARR * RB;        // 1 KB blocks per stage
+    static constexpr int LPW = STAGE / 4;          // loads per wave per stage
+    static constexpr int S = SPLIT ? 4 : 8;        // ring depth (32 / 64 KB at T = 128)
 };
 
-// buf: one LDS buffer, [narr][blk_n][64] uint4 flattened; the counts are
+// One stage's loads into buf ([narr][rb_n][64] uint4); the counts are
 // compile-time constants at every (inlined) call.  Row blocks past the padded
 // operand (a ragged last tile) load its last block; their outputs are never
 // stored.
-__device__ __forceinline__ void gram_issue(uint4 *buf, int narr, int blk_n, const uint4 *__restrict__ hi,
+__device__ __forceinline__ void gram_issue(uint4 *buf, int narr, int rb_n, const uint4 *__restrict__ hi,
                                            const uint4 *__restrict__ lo, int64_t I0, int64_t J0, int64_t rbmax,
-                                           int64_t KB, int64_t kb0, int wave, int lane) {
+                                           int64_t KB, int64_t kb, int wave, int lane) {
 #pragma unroll
-    for (int t = 0; t < narr * blk_n / 4; ++t) {
-        const int gb = wave + 4 * t;  // 0 .. narr * blk_n - 1
-        const int arr = gb / blk_n, blk = gb % blk_n, mb = blk >> 1, ks = blk & 1;
+    for (int t = 0; t < narr * rb_n / 4; ++t) {
+        const int gb = wave + 4 * t;  // 0 .. narr * rb_n - 1
+        const int arr = gb / rb_n, mb = gb % rb_n;
         const uint4 *src = (arr & 2) ? lo : hi;
         int64_t rb = (((arr & 1) ? J0 : I0) >> 5) + mb;
         rb = rb < rbmax ? rb : rbmax;
-        __builtin_amdgcn_global_load_lds(src + (rb * KB + kb0 + ks) * 64 + lane, buf + (arr * blk_n + blk) * 64,
-                                         16, 0, 0);
+        __builtin_amdgcn_global_load_lds(src + (rb * KB + kb) * 64 + lane, buf + gb * 64, 16, 0, 0);
     }
+}
+
+// s_waitcnt with vmcnt <= N (N < 64) and no wait on the other counters.
+template <int N>
+__device__ __forceinline__ void wait_vm() {
+    __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | (7 << 4) | (15 << 8));
+}
+template <int LPW, int A>
+__device__ __forceinline__ void wait_vm_ahead(int ahead) {
+    if constexpr (A < 0) {
+        return;
+    } else {
+        if (ahead == A) wait_vm<A * LPW>();
+        else wait_vm_ahead<LPW, A - 1>(ahead);
+    }
+}
+
+// Operand fragments are read from the ring with ds_read_b128 written out as
+// inline assembly: the compiler does not model the LDS writes of the
+// global-to-LDS loads, so it would either wait for every load in flight
+// before each LDS read or treat the ring as never written.  The reads are
+// waited for explicitly (lds_wait), and that wait names the fragment
+// registers so no use can move above it.
+__device__ __forceinline__ uint32_t lds_addr(const void *p) {
+    return static_cast<uint32_t>(reinterpret_cast<uintptr_t>(p));
+}
+__device__ __forceinline__ bf16x8_t lds_frag(uint32_t addr) {
+    bf16x8_t v;
+    asm volatile("ds_read_b128 %0, %1" : "=v"(v) : "v"(addr) : "memory");
+    return v;
+}
+template <int NP, int MT>
+__device__ __forceinline__ void lds_wait(bf16x8_t (&a)[NP][MT], bf16x8_t (&b)[NP][MT]) {
+    asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+#pragma unroll
+    for (int p = 0; p < NP; ++p)
+#pragma unroll
+        for (int m = 0; m < MT; ++m) asm volatile("" : "+v"(a[p][m]), "+v"(b[p][m]));
 }
 
 template <int MAP, bool SPLIT, bool STATS, int WT>
@@ -137,13 +181,14 @@ __global__ __launch_bounds__(kGramThreads) void edm_gram_kernel(MapGeom g, const
                                                                float *__restrict__ D,
                                                                unsigned long long *slots) {
     using C = GramCfg<SPLIT, WT>;
-    constexpr int T = C::T, MT = C::MT, NP = SPLIT ? 2 : 1;
+    constexpr int T = C::T, MT = C::MT, NP = SPLIT ? 2 : 1, S = C::S;
+    constexpr int BUF = C::STAGE * 64;  // uint4 per ring slot
+    static_assert(S * BUF * 16 >= 4 * 32 * WT * 4, "the epilogue stages 32 rows per wave in the ring");
     uint64_t lin;
     int TX, TY;
     if (!tile2_of<MAP, true>(g, lin, TX, TY)) return;
-    constexpr int BUF = C::NARR * C::BLK * 64;  // uint4 per LDS buffer
-    __shared__ __attribute__((aligned(16))) uint4 Lb[2 * BUF];
-    __shared__ float nA[T], nB[T];
+    __shared__ __attribute__((aligned(16))) uint4 Lb[S * BUF];
+    __shared__ __attribute__((aligned(16))) float nA[T], nB[T];
 
     const int t = threadIdx.x;
     const int lane = t & 63, w = t >> 6, wm = w >> 1, wn = w & 1;
@@ -163,64 +208,89 @@ __global__ __launch_bounds__(kGramThreads) void edm_gram_kernel(MapGeom g, const
 #pragma unroll
             for (int e = 0; e < 16; ++e) acc[m][c][e] = 0.f;
 
-    const int nst = int(dpad / kGramK);
+    const int nst = int(dpad / 16);  // 16-wide k steps
     const int64_t KB = dpad / 16, rbmax = gram_rows(n) / 32 - 1;
     const uint4 *hi4 = reinterpret_cast<const uint4 *>(hi), *lo4 = reinterpret_cast<const uint4 *>(lo);
-    gram_issue(Lb, C::NARR, C::BLK, hi4, lo4, I0, J0, rbmax, KB, 0, w, lane);
-    for (int s = 0; s < nst; ++s) {
-        __builtin_amdgcn_s_waitcnt(0);  // this wave's loads of chunk s have landed
-        __syncthreads();                // ... and every wave's; chunk s - 1 is consumed
-        const uint4 *cur = Lb + (s & 1) * BUF;
+    for (int p = 0; p < S - 1 && p < nst; ++p)
+        gram_issue(Lb + p * BUF, C::NARR, C::RB, hi4, lo4, I0, J0, rbmax, KB, p, w, lane);
+    const uint32_t ring = lds_addr(Lb);
+    for (int st = 0; st < nst; ++st) {
+        const int ahead = nst - 1 - st < S - 2 ? nst - 1 - st : S - 2;
+        wait_vm_ahead<C::LPW, S - 2>(ahead);  // this wave's loads of step st have landed
+        __builtin_amdgcn_s_barrier();           // ... and every wave's; step st - 1 is consumed
+        if (st + S - 1 < nst)
+            gram_issue(Lb + ((st + S - 1) % S) * BUF, C::NARR, C::RB, hi4, lo4, I0, J0, rbmax, KB, st + S - 1, w,
+                       lane);
+        const uint32_t cur = ring + uint32_t((st % S) * BUF) * 16u + uint32_t(lane) * 16u;
+        bf16x8_t a[NP][MT], b[NP][MT];  // [hi, lo][sub-tile]
 #pragma unroll
-        for (int ks = 0; ks < 2; ++ks) {
-            bf16x8_t a[NP][MT], b[NP][MT];  // [hi, lo][sub-tile]
+        for (int p = 0; p < NP; ++p)
 #pragma unroll
-            for (int p = 0; p < NP; ++p)
+            for (int m = 0; m < MT; ++m) {
+                a[p][m] = lds_frag(cur + uint32_t(((2 * p) * C::RB + wm * MT + m) * 64 * 16));
+                b[p][m] = lds_frag(cur + uint32_t(((2 * p + 1) * C::RB + wn * MT + m) * 64 * 16));
+            }
+        lds_wait<NP, MT>(a, b);
 #pragma unroll
-                for (int m = 0; m < MT; ++m) {
-                    a[p][m] = __builtin_bit_cast(bf16x8_t, cur[((2 * p) * C::BLK + (wm * MT + m) * 2 + ks) * 64 + lane]);
-                    b[p][m] = __builtin_bit_cast(bf16x8_t,
-                                                 cur[((2 * p + 1) * C::BLK + (wn * MT + m) * 2 + ks) * 64 + lane]);
-                }
-            if (ks == 0 && s + 1 < nst)
-                gram_issue(Lb + ((s + 1) & 1) * BUF, C::NARR, C::BLK, hi4, lo4, I0, J0, rbmax, KB,
-                           int64_t(s + 1) * (kGramK / 16), w, lane);
-#pragma unroll
-            for (int m = 0; m < MT; ++m)
-#pragma unroll
-                for (int c = 0; c < MT; ++c) {
-                    acc[m][c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[0][m], b[0][c], acc[m][c], 0, 0, 0);
-                    if (SPLIT) {
-                        acc[m][c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[0][m], b[NP - 1][c], acc[m][c],
-                                                                            0, 0, 0);
-                        acc[m][c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[NP - 1][m], b[0][c], acc[m][c],
-                                                                            0, 0, 0);
-                    }
-                }
-        }
-    }
-
-    // 32 x 32 accumulator layout: lane l, element e holds row
-    // (e & 3) + 4 (l >> 5) + 8 (e >> 2) and column l & 31 of the MFMA tile.
-#pragma unroll
-    for (int m = 0; m < MT; ++m)
-#pragma unroll
-        for (int e = 0; e < 16; ++e) {
-            const int il = wm * WT + m * 32 + (e & 3) + 4 * (lane >> 5) + 8 * (e >> 2);
-            const int64_t i = I0 + il;
-            if (i >= n) continue;
-            const int64_t rowbase = i * n - (i * (i - 1)) / 2 - i;
+        for (int m = 0; m < MT; ++m)
 #pragma unroll
             for (int c = 0; c < MT; ++c) {
-                const int jl = wn * WT + c * 32 + (lane & 31);
-                const int64_t j = J0 + jl;
-                if (j < n && (!diag || j >= i)) {
-                    float v = __builtin_fmaf(-2.f, acc[m][c][e], nA[il] + nB[jl]);
-                    v = (i == j) ? 0.f : fmaxf(v, 0.f);
-                    __builtin_nontemporal_store(v, D + rowbase + j);
+                acc[m][c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[0][m], b[0][c], acc[m][c], 0, 0, 0);
+                if (SPLIT) {
+                    acc[m][c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[0][m], b[NP - 1][c], acc[m][c], 0, 0, 0);
+                    acc[m][c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[NP - 1][m], b[0][c], acc[m][c], 0, 0, 0);
                 }
             }
+    }
+
+    // Epilogue.  32 x 32 accumulator layout: lane l, element e holds row
+    // (e & 3) + 4 (l >> 5) + 8 (e >> 2) and column l & 31 of the MFMA tile.
+    // Per pass m each wave stages its 32 x WT slice of D in the (now idle)
+    // ring, then writes every row's WT floats as contiguous 16-byte pieces,
+    // so each store instruction covers whole runs of the packed row.  Tiles
+    // off the diagonal and inside n (all but a thin fringe) store unmasked.
+    __syncthreads();
+    float *St = reinterpret_cast<float *>(Lb) + w * 32 * WT;
+    constexpr int LPR = WT / 4;  // lanes per staged row
+    const bool interior = !diag && I0 + T <= n && J0 + T <= n;
+    float nb[MT];
+#pragma unroll
+    for (int c = 0; c < MT; ++c) nb[c] = nB[wn * WT + c * 32 + (lane & 31)];
+#pragma unroll
+    for (int m = 0; m < MT; ++m) {
+        float na[16];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const float4 r4 = *reinterpret_cast<const float4 *>(&nA[wm * WT + m * 32 + 8 * q + 4 * (lane >> 5)]);
+            na[4 * q + 0] = r4.x; na[4 * q + 1] = r4.y; na[4 * q + 2] = r4.z; na[4 * q + 3] = r4.w;
         }
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+            const int rl = (e & 3) + 4 * (lane >> 5) + 8 * (e >> 2);
+#pragma unroll
+            for (int c = 0; c < MT; ++c) {
+                float v = fmaxf(__builtin_fmaf(-2.f, acc[m][c][e], na[e] + nb[c]), 0.f);
+                // on a diagonal tile, element (il, il) is the diagonal: exactly 0
+                v = (diag && wm * WT + m * 32 + rl == wn * WT + c * 32 + (lane & 31)) ? 0.f : v;
+                St[rl * WT + c * 32 + (lane & 31)] = v;
+            }
+        }
+#pragma unroll
+        for (int it = 0; it < 32 * LPR / 64; ++it) {
+            const int rl = it * (64 / LPR) + lane / LPR, cl = 4 * (lane % LPR);
+            const int64_t i = I0 + wm * WT + m * 32 + rl, j = J0 + wn * WT + cl;
+            const float4 v = *reinterpret_cast<const float4 *>(St + rl * WT + cl);
+            float *dst = D + (i * n - (i * (i - 1)) / 2 - i) + j;
+            if (interior) {
+                *reinterpret_cast<float4 *>(dst) = v;  // 4-byte aligned: the packed rows start anywhere
+            } else if (i < n) {
+                const float vv[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    if (j + q < n && j + q >= i) dst[q] = vv[q];
+            }
+        }
+    }
     if (STATS) {
         __shared__ unsigned long long red[2][kGramThreads / kWave];
         unsigned long long cnt, cs;
@@ -249,13 +319,9 @@ int launch_edm_gram(const MapGeom &g, int tile, const uint16_t *hi, const uint16
     prof_begin(K_EDM_GRAM, s);
     map_switch(int(g.map), [&](auto M) {
         constexpr int MAPK = decltype(M)::value;
-        if (tile == 256) {
-            if (split) go_gram<MAPK, true, 128>(g, hi, lo, norms, n, dpad, D, slots, s);
-            else go_gram<MAPK, false, 128>(g, hi, lo, norms, n, dpad, D, slots, s);
-        } else {
-            if (split) go_gram<MAPK, true, 64>(g, hi, lo, norms, n, dpad, D, slots, s);
-            else go_gram<MAPK, false, 64>(g, hi, lo, norms, n, dpad, D, slots, s);
-        }
+        (void)tile;  // kGramTile
+        if (split) go_gram<MAPK, true, kGramTile / 2>(g, hi, lo, norms, n, dpad, D, slots, s);
+        else go_gram<MAPK, false, kGramTile / 2>(g, hi, lo, norms, n, dpad, D, slots, s);
     });
     prof_end(K_EDM_GRAM, s);
     return check_launch("edm_packed (gram)");

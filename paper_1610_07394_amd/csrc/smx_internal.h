@@ -65,9 +65,8 @@ int launch_count(int m, const MapGeom &g, int64_t n, int rho, int map, int stric
 // FP32 difference form: 128 x 128 tiles (8 x 8 per thread) once there are
 // enough of them to fill the chip, 64 x 64 (4 x 4 per thread) below that.
 inline int edm_diff_tile(int64_t n) { return n >= 8192 ? 128 : 64; }
-// Gram form: 256 x 256 tiles from n = 16384 (enough tiles to fill the chip
-// several times over), 128 x 128 below.
-inline int gram_tile(int64_t n) { return n >= 16384 ? 256 : 128; }
+constexpr int kGramTile = 128;   // Gram form: 128 x 128 elements per block
+inline int gram_tile(int64_t) { return kGramTile; }
 constexpr int kGramK = 32;       // Gram K padding
 // rows of the fragment-ordered BF16 operands (zero padded to a 32-row block)
 __host__ __device__ inline int64_t gram_rows(int64_t n) { return (n + 31) / 32 * 32; }

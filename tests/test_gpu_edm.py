@@ -182,10 +182,10 @@ def test_edm_full_size_gram(prec):
 
 
 @pytest.mark.parametrize("prec", ["bf16", "split_bf16"])
-def test_edm_gram_large_tile_ragged(prec):
-    """n = 16484 (256-element Gram tiles, the last one ragged), d = 40 (K padded
-    to 64): all maps bit-identical; sampled rows at tile edges against the
-    oracle."""
+def test_edm_gram_large_n_ragged(prec):
+    """n = 16484 (128-element Gram tiles, the last one ragged, 32-row operand
+    blocks padded), d = 40 (K padded to 64, a partial ring of k steps): all
+    maps bit-identical; sampled rows at tile edges against the oracle."""
     n, d = 16484, 40
     X = np.random.default_rng(11).standard_normal((n, d)).astype(np.float32)
     Xt = torch.from_numpy(X).cuda()
@@ -193,7 +193,7 @@ def test_edm_gram_large_tile_ragged(prec):
     for kind in KINDS[1:]:
         assert torch.equal(D, smx.edm_packed(Xt, kind, prec)), kind
     torch.cuda.synchronize()
-    rows = [0, 1, 255, 256, 511, 8191, 8192, 16383, 16384, n - 2, n - 1]
+    rows = [0, 1, 127, 128, 255, 256, 8191, 8192, 16383, 16384, n - 101, n - 100, n - 2, n - 1]
     nrm = (X.astype(np.float64) ** 2).sum(1)
     worst = 0.0
     for i in rows:
