@@ -166,10 +166,34 @@ def main():
         t = ms / c / 1e3
         e = elements["gram"]
         byts = 4 * e + 2 * N_GRAM * D_GRAM * 2  # packed FP32 output + the BF16 operand once
+        # measured write ceilings on this GPU for the same 2.15 GB output: a plain
+        # streaming fill of the buffer, and the packed-triangle tile stores of the
+        # same kernel with 32 input dimensions (1/16 of the matrix-core work)
+        fill = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        D3.fill_(0.0)
+        fill[0].record()
+        for _ in range(args.steps):
+            D3.fill_(1.0)
+        fill[1].record()
+        torch.cuda.synchronize()
+        t_fill = fill[0].elapsed_time(fill[1]) / args.steps / 1e3
+        X3s = X3[:, :32].contiguous()
+        smx.edm_packed(X3s, "lambda", "bf16", out=D3, ws=ws3)
+        torch.cuda.synchronize()
+        smx.profile_enable(True)
+        smx.profile_reset()
+        for _ in range(args.steps):
+            smx.edm_packed(X3s, "lambda", "bf16", out=D3, ws=ws3)
+        ms32, c32 = smx.profile_read("edm_gram")
+        smx.profile_enable(False)
+        del X3s
         comps["edm_bf16_n32768_d512"] = {
             "elements": e, "kernel_ms": ms / c, "elements_per_s": e / t,
             "mfma_tflops": 2 * D_GRAM * e / t / 1e12, "mfma_frac": 2 * D_GRAM * e / t / PEAK_BF16,
-            "hbm_gbs": byts / t / 1e9, "hbm_frac": byts / t / PEAK_HBM}
+            "hbm_gbs": byts / t / 1e9, "hbm_frac": byts / t / PEAK_HBM,
+            "write_ceiling_fill_gbs": 4 * e / t_fill / 1e9,
+            "write_ceiling_packed_d32_ms": ms32 / c32,
+            "frac_of_packed_d32": (ms32 / c32) / (ms / c)}
     if "at" in only:
         t = kavg["triplet_grad"] / 1e3
         tri = math.comb(N_AT, 3)

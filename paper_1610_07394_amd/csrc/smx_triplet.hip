@@ -48,6 +48,8 @@
 //      half a wave per pair set), x_a sum_b W_ab - sum_b W_ab x_b, FP64
 //      atomics into the gradient;
 //   5. energy: wave / block sums in FP64, one atomic into a spread slot.
+#include <type_traits>
+
 #include "smx_device.h"
 #include "smx_internal.h"
 
@@ -123,8 +125,11 @@ __global__ __launch_bounds__(kTripThreads, 3) void at_kernel(MapGeom g, const fl
     // set 2 rows k (Z) cols j (Y).  Valid iff the pair is in triplet order
     // (i < j, i < k, j < k) and the larger index is < n.  Thread t takes
     // column t % 32 and rows t / 32 + 8 it of every set; indices fit 32 bits
-    // (n < 2^31, tile bases < n + 32).
-    {
+    // (n < 2^31, tile bases < n + 32).  An interior tile (X < Y < Z, all of it
+    // below n: nearly every block) has only valid pairs and skips the test.
+    const bool interior = TX < TY && TY < TZ && base[2] + kTripTile <= n;
+    auto pair_terms = [&](auto full) {
+        constexpr bool FULL = decltype(full)::value;
         const int c = t & 31, r0 = t >> 5;
         const uint32_t un = uint32_t(n);
         const uint32_t bt[3] = {uint32_t(base[0]), uint32_t(base[1]), uint32_t(base[2])};
@@ -140,7 +145,7 @@ __global__ __launch_bounds__(kTripThreads, 3) void at_kernel(MapGeom g, const fl
                 const float dx = pb.x - pa.x, dy = pb.y - pa.y, dz = pb.z - pa.z;
                 const float sv = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dx * dx));
                 const uint32_t ga = bt[ta] + uint32_t(r);
-                const bool valid = set == 0 ? (ga < gb && gb < un) : (gb < ga && ga < un);
+                const bool valid = FULL || (set == 0 ? (ga < gb && gb < un) : (gb < ga && ga < un));
                 const float d = valid ? __builtin_amdgcn_rsqf(sv) : 0.f;
                 const float rs = d * d;
                 const int o = r * kTripLd + c;
@@ -149,7 +154,9 @@ __global__ __launch_bounds__(kTripThreads, 3) void at_kernel(MapGeom g, const fl
                 if (GRAD && set != 0) plane(M4_KI + set - 1)[o] = -4.f * sv;
             }
         }
-    }
+    };
+    if (interior) pair_terms(std::true_type{});
+    else pair_terms(std::false_type{});
     __syncthreads();
 
     // lane = 16 row + 4 q + e;  ib = 4 (row >> 1) + q,  jb = 4 (row & 1) + e;
@@ -274,7 +281,7 @@ __global__ __launch_bounds__(kTripThreads, 3) void at_kernel(MapGeom g, const fl
         for (int a = 0; a < 4; ++a) {
 #pragma unroll
             for (int b = 0; b < 4; ++b)
-                w1[a][b] = f1[a][b] != 0.f ? w1[a][b] * __builtin_amdgcn_rcpf(s1[a][b]) : 0.f;
+                w1[a][b] = (interior || f1[a][b] != 0.f) ? w1[a][b] * __builtin_amdgcn_rcpf(s1[a][b]) : 0.f;
             *reinterpret_cast<float4 *>(plane(2 + kb) + (4 * ib + a) * kTripLd + 4 * jb) =
                 make_float4(w1[a][0], w1[a][1], w1[a][2], w1[a][3]);
         }
