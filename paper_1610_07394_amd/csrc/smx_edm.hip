@@ -110,15 +110,18 @@ __global__ __launch_bounds__(kEdmThreads, 3) void edm_diff_kernel(MapGeom g, con
         __syncthreads();
     }
 
+    // a tile off the diagonal and inside n (nearly every block) stores unmasked
+    const bool interior = !diag && r0 + T <= n && c0 + T <= n;
 #pragma unroll
     for (int r = 0; r < MT; ++r) {
         const int64_t i = r0 + ty + 16 * r;
-        if (i >= n) continue;
-        const int64_t rowbase = i * n - (i * (i - 1)) / 2 - i;  // p(i, j) = rowbase + j
+        if (!interior && i >= n) continue;
+        float *row = D + (i * n - (i * (i - 1)) / 2 - i) + c0 + tx;  // p(i, j) = i n - i(i-1)/2 + (j - i)
 #pragma unroll
         for (int c = 0; c < MT; ++c) {
             const int64_t j = c0 + tx + 16 * c;
-            if (j < n && (!diag || j >= i)) __builtin_nontemporal_store(acc[r][c], D + rowbase + j);
+            // plain stores: measured faster than non-temporal ones here
+            if (interior || (j < n && (!diag || j >= i))) row[16 * c] = acc[r][c];
         }
     }
     if (STATS) {
