@@ -61,6 +61,7 @@ def lib():
         L.orc_at_energy.argtypes = [_ptr, _i64, _i64, _dbl, _i64, _i64]
         L.orc_at_energy.restype = _dbl
         L.orc_at_grad.argtypes = [_ptr, _i64, _i64, _dbl, _ptr]
+        L.orc_at_triplet_rows.argtypes = [_ptr, _i64, _i64, _dbl, _i64, _i64, _ptr]
         L.orc_at_grad_rows.argtypes = [_ptr, _i64, _i64, _dbl, _ptr, _i64, _ptr]
         L.orc_lj_energy.argtypes = [_ptr, _i64, _i64, _dbl, _dbl, _dbl]
         L.orc_lj_energy.restype = _dbl
@@ -116,6 +117,21 @@ def at_energy(X: np.ndarray, nu: float = 1.0, i0: int = 0, i1: int | None = None
     X = _f32(X)
     n = X.shape[0]
     return lib().orc_at_energy(X.ctypes.data, n, X.shape[1], nu, i0, n if i1 is None else i1)
+
+
+def triplet_rows_len(n: int, i0: int, i1: int) -> int:
+    """Elements of rows [i0, i1) of the packed triplet array: sum of C(n-1-i, 2)."""
+    return sum((n - 1 - i) * (n - 2 - i) // 2 for i in range(i0, i1))
+
+
+def at_triplet_rows(X: np.ndarray, nu: float = 1.0, i0: int = 0, i1: int | None = None) -> np.ndarray:
+    """Per-triplet energies of rows [i0, i1), triplets i < j < k in lexicographic order."""
+    X = _f32(X)
+    n = X.shape[0]
+    i1 = n if i1 is None else i1
+    out = np.empty(triplet_rows_len(n, i0, i1), dtype=np.float64)
+    lib().orc_at_triplet_rows(X.ctypes.data, n, X.shape[1], nu, i0, i1, out.ctypes.data)
+    return out
 
 
 def at_grad(X: np.ndarray, nu: float = 1.0) -> np.ndarray:

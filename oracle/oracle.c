@@ -118,6 +118,23 @@ double orc_at_energy(const float *X, int64_t n, int64_t ldx, double nu,
     return e;
 }
 
+/* Packed per-triplet energies, the 3-simplex analogue of the packed EDM: the
+ * triplets i < j < k < n in lexicographic order.  Rows i in [i0, i1) are
+ * written contiguously, starting with (i0, i0+1, i0+2), in exactly the order
+ * of the triple loop (row i holds C(n-1-i, 2) elements).                       */
+void orc_at_triplet_rows(const float *X, int64_t n, int64_t ldx, double nu,
+                         int64_t i0, int64_t i1, double *out)
+{
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t i = i0; i < i1; ++i) {
+        int64_t o = 0; /* elements of rows i0 .. i-1 */
+        for (int64_t r = i0; r < i; ++r) o += (n - 1 - r) * (n - 2 - r) / 2;
+        for (int64_t j = i + 1; j < n; ++j)
+            for (int64_t k = j + 1; k < n; ++k)
+                out[o++] = at_term_angle(X, ldx, i, j, k, nu);
+    }
+}
+
 /* Analytic gradient of one Axilrod-Teller term with respect to the three
  * positions.  With s1=|x_j-x_i|^2, s2=|x_k-x_j|^2, s3=|x_i-x_k|^2 the term is
  *   E = nu (P - 3/8 T) P^(-5/2),  P = s1 s2 s3,  T = t1 t2 t3,

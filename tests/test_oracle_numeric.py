@@ -115,6 +115,36 @@ def test_at_energy_row_ranges_add_up():
     assert parts == pytest.approx(e, rel=1e-13)
 
 
+def test_at_triplet_rows_element_by_element():
+    """Packed per-triplet energies: lexicographic i < j < k order, each element
+    equal to the independent s-form of that triplet."""
+    X = synth.rsa(11, seed=23, side=4.0, dmin=0.5)
+    P = X.astype(np.float64).tolist()
+    want = [_at_sform_py(P[i], P[j], P[k], nu=0.8) for i, j, k in itertools.combinations(range(11), 3)]
+    got = oracle.at_triplet_rows(X, nu=0.8)
+    assert got.shape == (math.comb(11, 3),)
+    np.testing.assert_allclose(got, want, rtol=1e-12)
+
+
+def test_at_triplet_rows_slices_and_sum():
+    X = synth.rsa(40, seed=4, side=6.0, dmin=0.5)
+    full = oracle.at_triplet_rows(X)
+    assert full.size == math.comb(40, 3) == oracle.triplet_rows_len(40, 0, 40)
+    assert full.sum() == pytest.approx(oracle.at_energy(X), rel=1e-12)
+    cuts = [0, 1, 2, 17, 37, 38, 40]
+    parts = [oracle.at_triplet_rows(X, i0=a, i1=b) for a, b in zip(cuts, cuts[1:])]
+    np.testing.assert_array_equal(np.concatenate(parts), full)
+
+
+def test_at_triplet_rows_equilateral():
+    a = 1.5
+    X = np.array([[0, 0, 0], [a, 0, 0], [a / 2, a * math.sqrt(3) / 2, 0]], np.float32)
+    Xd = X.astype(np.float64)
+    r = float(np.prod([np.linalg.norm(Xd[i] - Xd[j]) for i, j in ((0, 1), (1, 2), (0, 2))])) ** (1 / 3)
+    (e,) = oracle.at_triplet_rows(X)
+    assert e == pytest.approx(11 / (8 * r ** 9), rel=2e-6)
+
+
 def test_at_homogeneity_and_invariance():
     X = synth.rsa(12, seed=4, side=5.0, dmin=0.5)
     e = oracle.at_energy(X)
