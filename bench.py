@@ -202,6 +202,39 @@ def main():
             "lj_ms": kavg["lj"], "triplets_per_s": tri / t,
             "alu_tflops": AT_FLOPS_FWD_BWD * tri / t / 1e12, "alu_frac": AT_FLOPS_FWD_BWD * tri / t / PEAK_FP32}
 
+    # packed per-triplet energies, n = 2048 (the write-bound 3-simplex workload;
+    # measured beside the step, not part of it)
+    if "at" in only and not args.no_compare:
+        Xp = torch.from_numpy(synth.workload_input("at_n2048")).to(dev)
+        npk = Xp.shape[0]
+        mpk = npk * (npk - 1) * (npk - 2) // 6
+        Ep = torch.empty(mpk, dtype=torch.float32, device=dev)
+        pk = {}
+        for kind in ("lambda", "bbox"):
+            smx.triplet_packed(Xp, 1.0, kind, out=Ep)
+            torch.cuda.synchronize()
+            smx.profile_enable(True)
+            smx.profile_reset()
+            for _ in range(args.steps):
+                smx.triplet_packed(Xp, 1.0, kind, out=Ep)
+            ms, c = smx.profile_read("triplet_packed")
+            smx.profile_enable(False)
+            pk[kind] = ms / c
+        ev = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev[0].record()
+        for _ in range(args.steps):
+            Ep.fill_(1.0)
+        ev[1].record()
+        torch.cuda.synchronize()
+        t_fill = ev[0].elapsed_time(ev[1]) / args.steps / 1e3
+        t = pk["lambda"] / 1e3
+        comps["at_packed_n2048"] = {
+            "triplets": mpk, "kernel_ms": pk["lambda"], "bbox_ms": pk["bbox"], "triplets_per_s": mpk / t,
+            "hbm_gbs": 4 * mpk / t / 1e9, "hbm_frac": 4 * mpk / t / PEAK_HBM,
+            "write_ceiling_fill_gbs": 4 * mpk / t_fill / 1e9,
+            "per_unit": "4 bytes written per triplet (i < j < k), 1.430e9 triplets per launch"}
+        del Ep, Xp
+
     # dominant kernel (largest time per step)
     per_step = {k: kern[k][0] / args.steps for k in kern}
     dom = max(per_step, key=per_step.get)

@@ -200,6 +200,22 @@ int smx_triplet_energy_backward(const float *d_X, int64_t n, int64_t ldx, const 
                                 int map, const double *d_gradE, float *d_dX, void *d_ws,
                                 size_t ws_bytes, void *stream);
 
+/* Packed per-triplet Axilrod-Teller energies (Sec. I: a 3-simplex problem
+ * whose output, like the packed EDM of a 2-simplex, is one value per simplex
+ * element; it needs no reduction, so it is bound by the stores).
+ *   d_X   FP32 [n][ldx], ldx >= 3; read only.
+ *   d_E   FP32 [n(n-1)(n-2)/6]: E[p(i,j,k)] = nu (1 + 3 cos g_i cos g_j cos g_k)
+ *         / (r_ij r_jk r_ik)^3 for every i < j < k < n, p the lexicographic rank
+ *         p(i,j,k) = C(n,3) - C(n-i,3) + (j-i-1)(n-1) - (j(j-1)/2 - i(i+1)/2)
+ *                    + (k-j-1).  FP32 arithmetic in the kernel.
+ *   map   smx_map (lambda3 over 32^3 tiles, or a baseline); the result does not
+ *         depend on it.
+ *   d_stats nullable; with d_ws of smx_workspace_bytes(0, n) bytes it counts
+ *         the stored elements (triplets lt) and their checksum.
+ * n <= 2^21 (SMX_EOVERFLOW beyond); n < 3 writes nothing. */
+int smx_triplet_packed(const float *d_X, int64_t n, int64_t ldx, double nu, int map, float *d_E, void *d_ws,
+                       size_t ws_bytes, int64_t *d_stats, void *stream);
+
 /* d_out[q] = gradE[0] * d_G[q] for q < 3n (FP32 out, FP64 scale): the backward
  * pass of smx_triplet_energy_grad's output, given the incoming gradient
  * d_gradE (FP64 device scalar).  d_out may alias d_G. */
@@ -209,7 +225,8 @@ int smx_scale_grad(const float *d_G, int64_t n, const double *d_gradE, float *d_
  * events on its own stream.  smx_profile_read synchronises on those events and
  * returns the summed duration (ms) and launch count of kernel `kernel_id`
  * (0 map2, 1 map3, 2 edm diff, 3 edm gram, 4 gram prep, 5 triplet energy,
- * 6 triplet grad, 7 lj, 8 finalize) since the last reset; it returns SMX_EINVAL
+ * 6 triplet grad, 7 lj, 8 finalize, 9 triplet packed) since the last reset; it
+ * returns SMX_EINVAL
  * for an unknown id.  smx_profile_reset clears the totals.  Host only. */
 int smx_profile_enable(int on);
 int smx_profile_reset(void);

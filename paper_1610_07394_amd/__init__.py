@@ -16,7 +16,7 @@ import torch
 
 __all__ = [
     "MAPS", "PRECS", "SmxError", "Pot", "lib", "volume", "parallel_blocks", "map_tiles_host",
-    "workspace_bytes", "simplex_map2", "simplex_map3", "simplex_count", "edm_packed", "triplet_energy",
+    "workspace_bytes", "simplex_map2", "simplex_map3", "simplex_count", "triplet_packed", "edm_packed", "triplet_energy",
     "triplet_energy_grad", "triplet_energy_backward", "TripletEnergy", "profile_enable",
     "profile_reset", "profile_read", "KERNELS",
 ]
@@ -27,7 +27,7 @@ LIB_PATH = os.path.join(_HERE, "libsmx.so")
 MAPS = {"lambda": 0, "bbox": 1, "linear": 2, "lambda_below": 3}
 PRECS = {"fp32": 0, "bf16": 1, "split_bf16": 2}
 KERNELS = {"map2": 0, "map3": 1, "edm_diff": 2, "edm_gram": 3, "gram_prep": 4,
-           "triplet_energy": 5, "triplet_grad": 6, "lj": 7, "finalize": 8}
+           "triplet_energy": 5, "triplet_grad": 6, "lj": 7, "finalize": 8, "triplet_packed": 9}
 
 _i32, _i64, _sz, _vp, _dbl = ctypes.c_int, ctypes.c_int64, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_double
 
@@ -77,6 +77,7 @@ def lib():
         for name in ("smx_simplex_map2", "smx_simplex_map3"):
             getattr(L, name).argtypes = [_i64, _i32, _i32, _i32, _vp, _vp, _vp, _sz, _vp]
         L.smx_simplex_count.argtypes = [_i32, _i64, _i32, _i32, _i32, _vp, _vp, _sz, _vp]
+        L.smx_triplet_packed.argtypes = [_vp, _i64, _i64, _dbl, _i32, _vp, _vp, _sz, _vp, _vp]
         L.smx_edm_packed.argtypes = [_vp, _i64, _i64, _i64, _i32, _i32, _vp, _vp, _sz, _vp, _vp]
         L.smx_triplet_energy.argtypes = [_vp, _i64, _i64, ctypes.POINTER(_Pot), _i32, _vp, _vp, _sz, _vp, _vp]
         L.smx_triplet_energy_grad.argtypes = [_vp, _i64, _i64, ctypes.POINTER(_Pot), _i32, _vp, _vp, _vp,
@@ -224,6 +225,22 @@ def triplet_energy(X: torch.Tensor, pot: Pot = Pot(), map="lambda", stats=False,
     c = pot._c()
     _check(lib().smx_triplet_energy(xp, n, ldx, ctypes.byref(c), _map(map), _ptr(E), _ptr(ws), ws.numel(),
                                     _ptr(s), _stream()))
+    return (E, s) if stats else E
+
+
+def triplet_packed(X: torch.Tensor, nu: float = 1.0, map="lambda", stats=False, out=None, ws=None):
+    """Per-triplet Axilrod-Teller energies, FP32 [n(n-1)(n-2)/6] in lexicographic
+    i < j < k order; with stats=True also the int64 [4] counters."""
+    xp, n, ldx = _xarg(X)
+    m = n * (n - 1) * (n - 2) // 6
+    E = out if out is not None else torch.empty(m, dtype=torch.float32, device=X.device)
+    if E.dtype != torch.float32 or E.numel() < m or not E.is_contiguous() or E.device != X.device:
+        raise ValueError("out must be a contiguous FP32 tensor of n(n-1)(n-2)/6 elements on X's device")
+    s = torch.zeros(4, dtype=torch.int64, device=X.device) if stats else None
+    if stats and ws is None:
+        ws = _ws(workspace_bytes(0, n), X.device)
+    _check(lib().smx_triplet_packed(xp, n, ldx, float(nu), _map(map), _ptr(E), _ptr(ws),
+                                    0 if ws is None else ws.numel(), _ptr(s), _stream()))
     return (E, s) if stats else E
 
 

@@ -394,6 +394,27 @@ int smx_triplet_energy_backward(const float *d_X, int64_t n, int64_t ldx, const 
     return triplet_run(2, d_X, n, ldx, pot, map, nullptr, d_dX, d_gradE, d_ws, ws_bytes, nullptr, stream);
 }
 
+int smx_triplet_packed(const float *d_X, int64_t n, int64_t ldx, double nu, int map, float *d_E, void *d_ws,
+                       size_t ws_bytes, int64_t *d_stats, void *stream) {
+    if (n < 0) return fail(SMX_EINVAL, "n must be >= 0");
+    if (n > (int64_t(1) << 21)) return fail(SMX_EOVERFLOW, "n = %lld exceeds 2^21 (C(n,3) must fit 63 bits)", (long long)n);
+    if (ldx < 3) return fail(SMX_EINVAL, "ldx (%lld) < 3", (long long)ldx);
+    if (map < 0 || map > 3) return fail(SMX_EINVAL, "unknown map %d", map);
+    if (d_stats != nullptr && (d_ws == nullptr || ws_bytes < kSlotBytes))
+        return fail(SMX_EINVAL, "statistics need a workspace of %zu bytes", kSlotBytes);
+    if (n >= 3 && (d_X == nullptr || d_E == nullptr)) return fail(SMX_EINVAL, "X and E must not be NULL");
+    unsigned long long *slots = d_stats ? reinterpret_cast<unsigned long long *>(d_ws) : nullptr;
+    int rc;
+    if (slots && (rc = launch_fill_u64(reinterpret_cast<uint64_t *>(slots), kSlotBytes / 8, S(stream)))) return rc;
+    MapGeom g{};
+    if (n >= 3) {
+        if (!make_geom(3, (n + kTripTile - 1) / kTripTile, map, g)) return SMX_EOVERFLOW;
+        if ((rc = launch_triplet_packed(g, d_X, n, ldx, float(nu), d_E, slots, S(stream)))) return rc;
+    }
+    if (slots) return launch_stats_finalize(slots, g.G, d_stats, S(stream));
+    return SMX_OK;
+}
+
 int smx_scale_grad(const float *d_G, int64_t n, const double *d_gradE, float *d_out, void *stream) {
     if (n < 0) return fail(SMX_EINVAL, "n must be >= 0");
     if (n > kMaxN) return fail(SMX_EOVERFLOW, "n exceeds 2^31 - 1");

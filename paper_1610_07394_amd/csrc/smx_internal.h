@@ -18,7 +18,7 @@ int check_launch(const char *what);
 // Kernel ids for the timing facility (match smx_profile_read).
 enum KernelId {
     K_MAP2 = 0, K_MAP3 = 1, K_EDM_DIFF = 2, K_EDM_GRAM = 3, K_GRAM_PREP = 4,
-    K_TRIP_ENERGY = 5, K_TRIP_GRAD = 6, K_LJ = 7, K_FINALIZE = 8, K_COUNT = 9
+    K_TRIP_ENERGY = 5, K_TRIP_GRAD = 6, K_LJ = 7, K_FINALIZE = 8, K_TRIP_PACKED = 9, K_COUNT = 10
 };
 void prof_begin(int kid, hipStream_t s);
 void prof_end(int kid, hipStream_t s);
@@ -85,6 +85,8 @@ int launch_triplet(const MapGeom &g, const float *X, int64_t n, int64_t ldx, flo
 int launch_lj(const MapGeom &g, const float *X, int64_t n, int64_t ldx, float eps, float sigma,
               float rc2, double *G64, double *eslots, unsigned long long *sslots, hipStream_t s);
 int launch_energy_finalize(const double *eslots, double *E, hipStream_t s);
+int launch_triplet_packed(const MapGeom &g, const float *X, int64_t n, int64_t ldx, float nu, float *E,
+                          unsigned long long *sslots, hipStream_t s);
 int launch_grad_finalize(const double *G64, int64_t n, const double *gradE, float *out,
                          hipStream_t s);
 int launch_scale_grad(const float *G, int64_t n, const double *gradE, float *out, hipStream_t s);

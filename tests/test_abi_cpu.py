@@ -113,6 +113,13 @@ def test_validation_errors_before_any_device_work():
     assert L.smx_simplex_count(2, 16, 1, 0, 0, null, ctypes.c_void_p(256), 1 << 20, null) == 1
     assert L.smx_simplex_count(3, 16, 1, 0, 0, ctypes.c_void_p(256), null, 0, null) == 1
     assert b"workspace" in L.smx_last_error()
+    # packed triplet energies: n past 2^21, bad ldx / map, NULL buffers, stats without workspace
+    assert L.smx_triplet_packed(null, (1 << 21) + 1, 3, 1.0, 0, null, null, 0, null, null) == 2
+    assert L.smx_triplet_packed(null, 10, 2, 1.0, 0, null, null, 0, null, null) == 1
+    assert L.smx_triplet_packed(null, 10, 3, 1.0, 7, null, null, 0, null, null) == 1
+    assert L.smx_triplet_packed(null, 10, 3, 1.0, 0, null, null, 0, null, null) == 1
+    assert L.smx_triplet_packed(ctypes.c_void_p(256), 10, 3, 1.0, 0, ctypes.c_void_p(256), null, 0,
+                                ctypes.c_void_p(256), null) == 1
     # EDM argument checks
     assert L.smx_edm_packed(null, 10, 0, 3, 0, 0, null, null, 0, null, null) == 1
     assert L.smx_edm_packed(null, 10, 3, 2, 0, 0, null, null, 0, null, null) == 1
