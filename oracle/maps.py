@@ -271,11 +271,59 @@ def below3_tiles(nb: int) -> np.ndarray:
     return np.concatenate(parts, axis=0) if parts else np.zeros((0, 3), np.int64)
 
 
-MAPS = {"lambda": 0, "bbox": 1, "linear": 2, "lambda_below": 3}
+# --------------------------------------------------------------------------
+# The recursive orthotope set of Sec. III-B, in the paper's own corner
+# coordinates: the simplex {p >= 0 : p_1 + ... + p_m <= nb' - 1} (eq. (1) with
+# the orthogonal corner at 0).  The map of a simplex of side s whose relative
+# origin is c is the cube phi(w, c) of side s/2 placed at c, followed by m maps of
+# side s/2 at c + (s/2) e_d, d = 1..m (for m = 3 "the top and the sides of the
+# cube"), repeated until the smallest block.  Reading kept here: the recursion
+# ends at a simplex of side 1, which is one block (so the set covers the
+# non-strict simplex, diagonal included).  Blocks are listed in the order of
+# that recursion (depth first: the cube x fastest, then the m sub-maps in axis
+# order).  A corner point p becomes the tile (p_1, p_1 + p_2[, p_1 + p_2 + p_3])
+# of T2 / T3; blocks whose last tile coordinate reaches nb are filtered (points
+# of a cube outside the simplex, and everything past nb when nb' > nb).
+def recursive_tiles(m: int, nb: int) -> np.ndarray:
+    nbp = next_pow2(nb)
+    parts = []
+
+    def rec(c, s):
+        if s == 1:
+            parts.append(np.array([c], dtype=np.int64))
+            return
+        h = s // 2
+        idx = np.arange(h ** m, dtype=np.int64)
+        cube = np.stack([idx // h ** d % h for d in range(m)], axis=1) + np.array(c, dtype=np.int64)
+        parts.append(cube)
+        for d in range(m):
+            c2 = list(c)
+            c2[d] += h
+            rec(tuple(c2), h)
+
+    rec((0,) * m, nbp)
+    p = np.concatenate(parts, axis=0)
+    t = np.cumsum(p, axis=1)
+    t[t[:, -1] >= nb] = FILTERED
+    return t
+
+
+def recursive_sub_maps(m: int, nb: int) -> int:
+    """Number of sub-orthotopes (map calls, one launch each) of the recursive
+    set of side next_pow2(nb): the cube of every recursion node plus the
+    single-block leaves, counted by walking the recursion."""
+    def cnt(s):
+        return 1 if s == 1 else 1 + m * cnt(s // 2)
+    return cnt(next_pow2(nb))
+
+
+MAPS = {"lambda": 0, "bbox": 1, "linear": 2, "lambda_below": 3, "recursive": 4, "recursive_launch": 5}
 
 
 def tiles(m: int, nb: int, kind: str) -> np.ndarray:
-    """Tile dump of map ``kind`` ('lambda', 'bbox', 'linear') for T2 (m=2) or T3 (m=3)."""
+    """Tile dump of map ``kind`` (a key of MAPS) for T2 (m=2) or T3 (m=3)."""
+    if kind in ("recursive", "recursive_launch"):  # one set; the launches differ
+        return recursive_tiles(m, nb)
     if m == 2:
         return {"lambda": lambda2_tiles, "bbox": bbox2_tiles, "linear": linear2_tiles,
                 "lambda_below": below2_tiles}[kind](nb)

@@ -254,3 +254,88 @@ def test_below3_block_count(nb):
     # far fewer blocks than "from above" just past a power of two
     if nb == 33:
         assert total < maps.lambda3_tiles(33).shape[0] / 5
+
+
+# --------------------------------------------------------------------------
+# Recursive orthotope sets of Sec. III-B (the O(log n) map and its one launch
+# per sub-orthotope), in the paper's corner coordinates.
+def test_recursive_golden_nb4():
+    lines = [ln.split() for ln in open(os.path.join(GOLDEN, "recursive_nb4.txt"))
+             if ln.strip() and not ln.startswith("#")]
+    for m in (2, 3):
+        rows = np.array([[int(v) for v in ln] for ln in lines if int(ln[0]) == m], dtype=np.int64)
+        t = maps.recursive_tiles(m, 4)
+        assert t.shape[0] == rows.shape[0] == (10 if m == 2 else 20)
+        np.testing.assert_array_equal(rows[:, 1], np.arange(rows.shape[0]))
+        np.testing.assert_array_equal(t, rows[:, 2 + m:])
+        # the golden corner points themselves lie in the corner simplex
+        assert (rows[:, 2:2 + m].sum(axis=1) <= 3).all()
+
+
+@pytest.mark.parametrize("m", [2, 3])
+@pytest.mark.parametrize("nb", [1, 2, 3, 4, 5, 7, 8, 9, 16, 17, 33, 64])
+def test_recursive_bijection(m, nb):
+    ok, msg = maps.check_bijection(maps.recursive_tiles(m, nb), m, nb)
+    assert ok, msg
+
+
+@pytest.mark.parametrize("k", range(0, 9))
+def test_recursive_block_counts(k):
+    """Blocks of the set of side n = 2^k: the paper's recursion V = (n/2)^m +
+    m V(n/2) (built here by _vol_rec, which ends at V(1) = 0) plus the m^k
+    single-block leaves kept by this reading; closed forms n(n+1)/2 (m = 2,
+    the triangle exactly) and (n^3 + 4 * 3^k) / 5 (m = 3, eq. of Sec. III-B with
+    the leaves)."""
+    n = 2 ** k
+    for m in (2, 3):
+        got = maps.recursive_tiles(m, n).shape[0]
+        assert got == _vol_rec(n, m, m) + m ** k
+    assert maps.recursive_tiles(2, n).shape[0] == n * (n + 1) // 2
+    assert 5 * maps.recursive_tiles(3, n).shape[0] == n ** 3 + 4 * 3 ** k
+    # every 2-D block maps; 3-D blocks outside the tetrahedron are the extra volume
+    assert (maps.recursive_tiles(2, n) >= 0).all()
+    assert (maps.recursive_tiles(3, n)[:, 0] >= 0).sum() == comb(n + 2, 3)
+
+
+@pytest.mark.parametrize("k", range(0, 10))
+def test_recursive_sub_map_counts(k):
+    """One map call per recursion node: (m^(k+1) - 1) / (m - 1) sub-orthotopes,
+    at least (n - 1) / 2 (Sec. III-B: linear in n or worse)."""
+    n = 2 ** k
+    for m in (2, 3):
+        c = maps.recursive_sub_maps(m, n)
+        assert c == (m ** (k + 1) - 1) // (m - 1)
+        assert c >= (n - 1) / 2
+
+
+def test_recursive_extra_volume_tends_to_one_fifth():
+    """The 3-branch set exceeds the tetrahedron by 1/5 in the limit (Sec. III-B)."""
+    prev = 0.0
+    for k in range(2, 9):
+        n = 2 ** k
+        t = maps.recursive_tiles(3, n)
+        extra = t.shape[0] / comb(n + 2, 3) - 1
+        assert prev <= extra < 0.2
+        prev = extra
+    assert prev > 0.17
+    n = 2 ** 40
+    assert abs(Fraction(n ** 3 + 4 * 3 ** 40, 5) / comb(n + 2, 3) - 1 - Fraction(1, 5)) < 1e-9
+
+
+@pytest.mark.parametrize("m", [2, 3])
+def test_recursive_first_blocks_are_the_main_cube(m):
+    """The first (n/2)^m blocks are phi(w, 0): corner points with every
+    coordinate below n/2, x fastest; the next blocks start the sub-map at
+    (n/2) e_1."""
+    n = 16
+    t = maps.recursive_tiles(m, n)
+    h = n // 2
+    head = t[:h ** m]
+    w = np.arange(h ** m)
+    q = np.stack([w // h ** d % h for d in range(m)], axis=1)
+    inside = q.sum(axis=1) < n
+    assert (head[~inside] == maps.FILTERED).all() and (m == 3 or inside.all())
+    p = np.diff(np.concatenate([np.zeros((head.shape[0], 1), np.int64), head], axis=1), axis=1)
+    np.testing.assert_array_equal(p[inside], q[inside])
+    nxt = t[h ** m]
+    assert tuple(nxt) == ((h, h) if m == 2 else (h, h, h))
