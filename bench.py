@@ -265,7 +265,7 @@ def main():
     compare = None
     if not args.no_compare:
         compare = {}
-        for kind in ("bbox", "linear"):
+        for kind in ("bbox", "linear", "recursive", "recursive_launch"):
             step(kind)  # warm
             torch.cuda.synchronize()
             smx.profile_enable(True)
@@ -276,17 +276,18 @@ def main():
             smx.profile_enable(False)
             compare[kind] = {k: (v[0] / v[1] if v[1] else None) for k, v in kk.items()}
         compare["lambda"] = {k: kavg[k] for k in ("edm_diff", "edm_gram", "triplet_grad", "lj")}
-        sp = {}
-        for k in ("edm_diff", "edm_gram", "triplet_grad"):
-            if compare["bbox"].get(k) and compare["lambda"].get(k):
-                sp[k] = compare["bbox"][k] / compare["lambda"][k]
-        compare["speedup_lambda_vs_bbox"] = sp
+        for base in ("bbox", "recursive", "recursive_launch"):
+            sp = {}
+            for k in ("edm_diff", "edm_gram", "triplet_grad"):
+                if compare[base].get(k) and compare["lambda"].get(k):
+                    sp[k] = compare[base][k] / compare["lambda"][k]
+            compare[f"speedup_lambda_vs_{base}"] = sp
         # map-only parallel spaces (paper-like granularity: rho = 16 pairs, rho = 8 triplets)
         # "visit" = every element of every mapped tile is touched (count + id
         # checksum); "count" = each mapped block adds its tile's closed-form
         # count, so the time is the map plus the launched blocks alone.
         mo = {}
-        for kind in ("lambda", "bbox", "linear", "lambda_below"):
+        for kind in ("lambda", "bbox", "linear", "lambda_below", "recursive", "recursive_launch"):
             for m, n, rho in ((2, N_EDM, 16), (3, N_AT, 8)):
                 visit = smx.simplex_map2 if m == 2 else smx.simplex_map3
                 runs = (("visit", lambda: visit(n, rho, kind, strict=(m == 3), tiles=False)),

@@ -44,6 +44,21 @@
  *                     below).  No filtered blocks in 2-D; in 3-D only those of
  *                     the lambda3 parts.  Block order: segment by segment, each
  *                     part in that order.
+ *     SMX_MAP_RECURSIVE  the O(log n) recursive map of Sec. III-B, one launch:
+ *                     the recursive orthotope set in the paper's corner
+ *                     coordinates p (sum of p <= nb' - 1) -- the cube of side
+ *                     s/2 at the origin, then m sub-maps of side s/2 at
+ *                     (s/2) e_d, recursively, down to single blocks -- with
+ *                     corner point p mapped to tile (p1, p1+p2[, p1+p2+p3]).
+ *                     Blocks in depth-first order; V = nb'(nb'+1)/2 blocks for
+ *                     m = 2 (none filtered) and (nb'^3 + 4 * 3^log2(nb')) / 5
+ *                     for m = 3 (1/5 extra in the limit).  Each block walks
+ *                     log2(nb') levels to find its tile.
+ *     SMX_MAP_RECURSIVE_LAUNCH  the same set and block order with one kernel
+ *                     launch per sub-orthotope (the recursive map calls the
+ *                     paper argues against): (3^(log2 nb' + 1) - 1) / 2
+ *                     launches for m = 3, 2 nb' - 1 for m = 2, all on `stream`
+ *                     in depth-first order.
  *   The map changes only the schedule.  EDM outputs are bit-identical across
  *   maps; energies and gradients agree to rounding (atomic order).
  * - Statistics (d_stats, nullable): int64[4] =
@@ -72,7 +87,14 @@ typedef enum {
     SMX_EHIP = 4         /* a HIP call or kernel launch failed */
 } smx_status;
 
-typedef enum { SMX_MAP_LAMBDA = 0, SMX_MAP_BBOX = 1, SMX_MAP_LINEAR = 2, SMX_MAP_LAMBDA_BELOW = 3 } smx_map;
+typedef enum {
+    SMX_MAP_LAMBDA = 0,
+    SMX_MAP_BBOX = 1,
+    SMX_MAP_LINEAR = 2,
+    SMX_MAP_LAMBDA_BELOW = 3,
+    SMX_MAP_RECURSIVE = 4,
+    SMX_MAP_RECURSIVE_LAUNCH = 5
+} smx_map;
 
 typedef enum {
     SMX_EDM_FP32_DIFF = 0,      /* sum_k (x_ik - x_jk)^2 in FP32 on the vector ALUs */

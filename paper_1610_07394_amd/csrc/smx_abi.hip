@@ -88,8 +88,13 @@ bool make_geom(int m, int64_t nb, int map, MapGeom &g) {
     memset(&g, 0, sizeof(g));
     g.nb = int32_t(nb);
     g.map = uint32_t(map);
+    g.dim = m;
     const uint64_t u = uint64_t(nb);
-    if (map == MAP_LAMBDA) {
+    if (map == MAP_REC || map == MAP_REC_LAUNCH) {
+        g.lg = ceil_log2_u64(u);
+        if (g.lg > 20) return fail(SMX_EOVERFLOW, "recursive grid too large (nb = %lld)", (long long)nb), false;
+        g.G = rec_blocks(m, g.lg);
+    } else if (map == MAP_LAMBDA) {
         g.lg = ceil_log2_u64(u);
         if (g.lg > 30) return fail(SMX_EOVERFLOW, "lambda grid too large (nb = %lld)", (long long)nb), false;
         const uint64_t g2 = lambda2_blocks(g.lg);
@@ -121,7 +126,7 @@ static int check_common(int m, int64_t n, int rho, int map, int maxrho) {
     if (n < 0) return fail(SMX_EINVAL, "n must be >= 0 (got %lld)", (long long)n);
     if (n > kMaxN) return fail(SMX_EOVERFLOW, "n = %lld exceeds 2^31 - 1", (long long)n);
     if (!pow2(rho) || rho > maxrho) return fail(SMX_EINVAL, "rho must be a power of two in [1, %d] (got %d)", maxrho, rho);
-    if (map < 0 || map > 3) return fail(SMX_EINVAL, "unknown map %d", map);
+    if (map < 0 || map > MAP_REC_LAUNCH) return fail(SMX_EINVAL, "unknown map %d", map);
     return SMX_OK;
 }
 
@@ -222,6 +227,7 @@ int smx_map_tiles_host(int m, int64_t n, int rho, int map, int64_t first, int64_
             if (map == MAP_LAMBDA) ok = lambda2(uint32_t(b), g.lg, g.nb, X, Y);
             else if (map == MAP_BBOX) { X = int(b % g.nb); Y = int(b / g.nb); ok = X <= Y; }
             else if (map == MAP_BELOW) ok = below2(b, uint32_t(g.nb), X, Y);
+            else if (map == MAP_REC || map == MAP_REC_LAUNCH) ok = rec2(uint32_t(b), g.lg, g.nb, uint32_t(g.G), X, Y);
             else { linear2(uint32_t(b), X, Y); ok = true; }
             o[0] = ok ? X : -1;
             o[1] = ok ? Y : -1;
@@ -231,6 +237,7 @@ int smx_map_tiles_host(int m, int64_t n, int rho, int map, int64_t first, int64_
                 X = int(b % g.nb); Y = int((b / g.nb) % g.nb); Z = int(b / (uint64_t(g.nb) * g.nb));
                 ok = X <= Y && Y <= Z;
             } else if (map == MAP_BELOW) ok = below3(b, uint32_t(g.nb), X, Y, Z);
+            else if (map == MAP_REC || map == MAP_REC_LAUNCH) ok = rec3(uint32_t(b), g.lg, g.nb, uint32_t(g.G), X, Y, Z);
             else { linear3(uint32_t(b), X, Y, Z); ok = true; }
             o[0] = ok ? X : -1;
             o[1] = ok ? Y : -1;
@@ -292,7 +299,7 @@ int smx_edm_packed(const float *d_X, int64_t n, int64_t d, int64_t ldx, int map,
     if (n > kMaxN) return fail(SMX_EOVERFLOW, "n exceeds 2^31 - 1");
     if (d < 1) return fail(SMX_EINVAL, "d must be >= 1 (got %lld)", (long long)d);
     if (ldx < d) return fail(SMX_EINVAL, "ldx (%lld) < d (%lld)", (long long)ldx, (long long)d);
-    if (map < 0 || map > 3) return fail(SMX_EINVAL, "unknown map %d", map);
+    if (map < 0 || map > MAP_REC_LAUNCH) return fail(SMX_EINVAL, "unknown map %d", map);
     if (prec < 0 || prec > 2) return fail(SMX_EINVAL, "unknown precision %d", prec);
     if (n == 0) return SMX_OK;
     if (d_X == nullptr || d_D == nullptr) return fail(SMX_EINVAL, "X and D must not be NULL");
@@ -339,7 +346,7 @@ static int triplet_run(int mode, const float *d_X, int64_t n, int64_t ldx, const
     if (n < 0) return fail(SMX_EINVAL, "n must be >= 0");
     if (n > kMaxN) return fail(SMX_EOVERFLOW, "n exceeds 2^31 - 1");
     if (ldx < 3) return fail(SMX_EINVAL, "ldx must be >= 3 (got %lld)", (long long)ldx);
-    if (map < 0 || map > 3) return fail(SMX_EINVAL, "unknown map %d", map);
+    if (map < 0 || map > MAP_REC_LAUNCH) return fail(SMX_EINVAL, "unknown map %d", map);
     int rc = check_pot(pot);
     if (rc) return rc;
     if (mode == 0 && d_E == nullptr) return fail(SMX_EINVAL, "E must not be NULL");
@@ -399,7 +406,7 @@ int smx_triplet_packed(const float *d_X, int64_t n, int64_t ldx, double nu, int 
     if (n < 0) return fail(SMX_EINVAL, "n must be >= 0");
     if (n > (int64_t(1) << 21)) return fail(SMX_EOVERFLOW, "n = %lld exceeds 2^21 (C(n,3) must fit 63 bits)", (long long)n);
     if (ldx < 3) return fail(SMX_EINVAL, "ldx (%lld) < 3", (long long)ldx);
-    if (map < 0 || map > 3) return fail(SMX_EINVAL, "unknown map %d", map);
+    if (map < 0 || map > MAP_REC_LAUNCH) return fail(SMX_EINVAL, "unknown map %d", map);
     if (d_stats != nullptr && (d_ws == nullptr || ws_bytes < kSlotBytes))
         return fail(SMX_EINVAL, "statistics need a workspace of %zu bytes", kSlotBytes);
     if (n >= 3 && (d_X == nullptr || d_E == nullptr)) return fail(SMX_EINVAL, "X and E must not be NULL");

@@ -22,6 +22,13 @@ __device__ __forceinline__ uint64_t launch_index() {
     return uint64_t(blockIdx.y) * gridDim.x + blockIdx.x;
 }
 
+// True for the tail blocks of a 2-D launch (logical index >= G), which hold no
+// position in a tile dump.
+template <int MAP>
+__device__ __forceinline__ bool launch_tail(const MapGeom &g) {
+    return MAP != MAP_BBOX && launch_index() >= g.G;
+}
+
 // Tile of this block under map MAP.  Returns false for a filtered block (and
 // for the tail of a 2-D launch, where lin >= G).  `lin` receives the logical
 // block index (the dump position).  XCD: renumber the dispatch order so that
@@ -41,6 +48,11 @@ __device__ __forceinline__ bool tile2_of(const MapGeom &g, uint64_t &lin, int &X
     lin = id;
     if (MAP == MAP_LAMBDA) return lambda2(id, g.lg, g.nb, X, Y);
     if (MAP == MAP_BELOW) return below2(id, uint32_t(g.nb), X, Y);
+    if (MAP == MAP_REC) return rec2(id, g.lg, g.nb, uint32_t(g.G), X, Y);
+    if (MAP == MAP_CUBE) {
+        lin = g.off + id;
+        return cube2(id, g, X, Y);
+    }
     linear2(id, X, Y);
     return true;
 }
@@ -60,6 +72,11 @@ __device__ __forceinline__ bool tile3_of(const MapGeom &g, uint64_t &lin, int &X
     lin = id;
     if (MAP == MAP_LAMBDA) return lambda3(id, g.lg, g.nb, g.main, X, Y, Z);
     if (MAP == MAP_BELOW) return below3(id, uint32_t(g.nb), X, Y, Z);
+    if (MAP == MAP_REC) return rec3(id, g.lg, g.nb, uint32_t(g.G), X, Y, Z);
+    if (MAP == MAP_CUBE) {
+        lin = g.off + id;
+        return cube3(id, g, X, Y, Z);
+    }
     linear3(id, X, Y, Z);
     return true;
 }

@@ -162,7 +162,7 @@ int launch_edm_diff(const MapGeom &g, int tile, const float *X, int64_t n, int64
                     unsigned long long *slots, hipStream_t s) {
     const bool vec = (ldx % 4 == 0) && (d % kEdmKc == 0) && ((reinterpret_cast<uintptr_t>(X) & 15) == 0);
     prof_begin(K_EDM_DIFF, s);
-    map_switch(int(g.map), [&](auto M) { go_edm_map<decltype(M)::value>(g, tile, vec, X, n, d, ldx, D, slots, s); });
+    for_each_launch(g, [&](auto M, const MapGeom &gg) { go_edm_map<decltype(M)::value>(gg, tile, vec, X, n, d, ldx, D, slots, s); });
     prof_end(K_EDM_DIFF, s);
     return check_launch("edm_packed (fp32 diff)");
 }

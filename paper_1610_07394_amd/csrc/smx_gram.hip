@@ -317,11 +317,11 @@ int launch_edm_gram(const MapGeom &g, int tile, const uint16_t *hi, const uint16
                     int64_t n, int64_t dpad, bool split, float *D, unsigned long long *slots,
                     hipStream_t s) {
     prof_begin(K_EDM_GRAM, s);
-    map_switch(int(g.map), [&](auto M) {
+    for_each_launch(g, [&](auto M, const MapGeom &gg) {
         constexpr int MAPK = decltype(M)::value;
         (void)tile;  // kGramTile
-        if (split) go_gram<MAPK, true, kGramTile / 2>(g, hi, lo, norms, n, dpad, D, slots, s);
-        else go_gram<MAPK, false, kGramTile / 2>(g, hi, lo, norms, n, dpad, D, slots, s);
+        if (split) go_gram<MAPK, true, kGramTile / 2>(gg, hi, lo, norms, n, dpad, D, slots, s);
+        else go_gram<MAPK, false, kGramTile / 2>(gg, hi, lo, norms, n, dpad, D, slots, s);
     });
     prof_end(K_EDM_GRAM, s);
     return check_launch("edm_packed (gram)");

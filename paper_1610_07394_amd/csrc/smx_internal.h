@@ -41,8 +41,46 @@ inline void map_switch(int map, F &&f) {
     case MAP_LAMBDA: f(std::integral_constant<int, MAP_LAMBDA>{}); break;
     case MAP_BBOX: f(std::integral_constant<int, MAP_BBOX>{}); break;
     case MAP_LINEAR: f(std::integral_constant<int, MAP_LINEAR>{}); break;
+    case MAP_REC: f(std::integral_constant<int, MAP_REC>{}); break;
+    case MAP_CUBE: f(std::integral_constant<int, MAP_CUBE>{}); break;
     default: f(std::integral_constant<int, MAP_BELOW>{}); break;
     }
+}
+
+// The sub-orthotopes of the recursive set in depth-first order, one launch
+// each: the cube of side 2^(lg-1) at corner origin p, then the m sub-maps of
+// side 2^(lg-1) at p + 2^(lg-1) e_d; a side-1 simplex is one block.  c.off
+// advances by the blocks of each launch.
+template <typename F>
+inline void rec_launches(MapGeom &c, int lg, int32_t p0, int32_t p1, int32_t p2, F &f) {
+    const int h = lg > 0 ? lg - 1 : 0;
+    c.c0 = p0;
+    c.c1 = p1;
+    c.c2 = p2;
+    c.lg = h;
+    c.G = uint64_t(1) << (c.dim * h);
+    f(std::integral_constant<int, MAP_CUBE>{}, static_cast<const MapGeom &>(c));
+    c.off += c.G;
+    if (lg == 0) return;
+    const int32_t s = int32_t(1) << h;
+    rec_launches(c, h, p0 + s, p1, p2, f);
+    rec_launches(c, h, p0, p1 + s, p2, f);
+    if (c.dim == 3) rec_launches(c, h, p0, p1, p2 + s, f);
+}
+
+// Call f(std::integral_constant<int, MAP>{}, geom) for every launch that the
+// map needs: once for a single-launch map, once per sub-orthotope (MAP_CUBE)
+// for MAP_REC_LAUNCH.
+template <typename F>
+inline void for_each_launch(const MapGeom &g, F &&f) {
+    if (g.map == MAP_REC_LAUNCH) {
+        MapGeom c = g;
+        c.map = MAP_CUBE;
+        c.off = 0;
+        rec_launches(c, g.lg, 0, 0, 0, f);
+        return;
+    }
+    map_switch(int(g.map), [&](auto M) { f(M, g); });
 }
 
 // Map geometry for m-dimensional work with nb tiles per dimension.

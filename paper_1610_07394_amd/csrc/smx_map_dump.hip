@@ -56,7 +56,7 @@ __global__ __launch_bounds__(kMapThreads) void map2_kernel(MapGeom g, int64_t n,
     uint64_t lin;
     int X = -1, Y = -1;
     const bool ok = tile2_of<MAP, false>(g, lin, X, Y);
-    if (MAP != MAP_BBOX && lin >= g.G) return;  // tail of a 2-D launch
+    if (launch_tail<MAP>(g)) return;
     if (tiles != nullptr && threadIdx.x == 0) {
         tiles[2 * lin + 0] = ok ? X : -1;
         tiles[2 * lin + 1] = ok ? Y : -1;
@@ -85,7 +85,7 @@ __global__ __launch_bounds__(kMapThreads) void map3_kernel(MapGeom g, int64_t n,
     uint64_t lin;
     int X = -1, Y = -1, Z = -1;
     const bool ok = tile3_of<MAP, false>(g, lin, X, Y, Z);
-    if (MAP != MAP_BBOX && lin >= g.G) return;
+    if (launch_tail<MAP>(g)) return;
     if (tiles != nullptr && threadIdx.x == 0) {
         tiles[3 * lin + 0] = ok ? X : -1;
         tiles[3 * lin + 1] = ok ? Y : -1;
@@ -166,7 +166,8 @@ __global__ __launch_bounds__(kMapThreads) void count3_kernel(MapGeom g, int64_t 
 int launch_count(int m, const MapGeom &g, int64_t n, int rho, int map, int strict,
                  unsigned long long *slots, hipStream_t s) {
     prof_begin(m == 2 ? K_MAP2 : K_MAP3, s);
-    map_switch(map, [&](auto M) {
+    (void)map;
+    for_each_launch(g, [&](auto M, const MapGeom &g) {
         constexpr int MAPK = decltype(M)::value;
         if (m == 2) {
             const dim3 grid = MAPK == MAP_BBOX ? dim3(g.nb, g.nb, 1) : grid_for(g.G, kMapThreads);
@@ -210,7 +211,8 @@ int launch_map2(const MapGeom &g, int64_t n, int rho, int map, int strict, int32
                 unsigned long long *slots, hipStream_t s) {
     const int lgrho = floor_log2_u32(uint32_t(rho));
     prof_begin(K_MAP2, s);
-    map_switch(map, [&](auto M) { go_map2<decltype(M)::value>(g, n, rho, lgrho, strict, tiles, slots, s); });
+    (void)map;
+    for_each_launch(g, [&](auto M, const MapGeom &gg) { go_map2<decltype(M)::value>(gg, n, rho, lgrho, strict, tiles, slots, s); });
     prof_end(K_MAP2, s);
     return check_launch("simplex_map2");
 }
@@ -219,7 +221,8 @@ int launch_map3(const MapGeom &g, int64_t n, int rho, int map, int strict, int32
                 unsigned long long *slots, hipStream_t s) {
     const int lgrho = floor_log2_u32(uint32_t(rho));
     prof_begin(K_MAP3, s);
-    map_switch(map, [&](auto M) { go_map3<decltype(M)::value>(g, n, rho, lgrho, strict, tiles, slots, s); });
+    (void)map;
+    for_each_launch(g, [&](auto M, const MapGeom &gg) { go_map3<decltype(M)::value>(gg, n, rho, lgrho, strict, tiles, slots, s); });
     prof_end(K_MAP3, s);
     return check_launch("simplex_map3");
 }

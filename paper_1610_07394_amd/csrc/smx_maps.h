@@ -19,7 +19,8 @@
 
 namespace smx {
 
-enum MapKind { MAP_LAMBDA = 0, MAP_BBOX = 1, MAP_LINEAR = 2, MAP_BELOW = 3 };
+// MAP_CUBE is internal: one sub-orthotope of MAP_REC_LAUNCH, launched alone.
+enum MapKind { MAP_LAMBDA = 0, MAP_BBOX = 1, MAP_LINEAR = 2, MAP_BELOW = 3, MAP_REC = 4, MAP_REC_LAUNCH = 5, MAP_CUBE = 6 };
 
 // floor(log2 v), v >= 1.  The paper's bit-level form (Sec. III-A) counts from
 // the word size W: floor(log2 v) = (W - 1) - clz(v), 2^floor(log2 v) = 1 << that.
@@ -34,10 +35,14 @@ SMX_HD int ceil_log2_u64(uint64_t v) {
 // Geometry shared by host sizing and device evaluation.
 struct MapGeom {
     int32_t nb;     // tiles per dimension
-    int32_t lg;     // log2 of nb' = next power of two >= nb (lambda maps)
+    int32_t lg;     // log2 of nb' = next power of two >= nb (lambda and recursive
+                    // maps); MAP_CUBE: log2 of the sub-orthotope's side
     uint32_t main;  // lambda3: blocks of the orthotope Pi3 (before the plane grid)
     uint32_t map;   // MapKind of the launch
     uint64_t G;     // logical blocks launched
+    int32_t dim;    // m, the simplex dimension
+    int32_t c0, c1, c2;  // MAP_CUBE: corner-coordinate origin of the sub-orthotope
+    uint64_t off;   // MAP_CUBE: position of its first block in the whole set
 };
 
 // ---------------------------------------------------------------- lambda2
@@ -286,6 +291,106 @@ SMX_HD bool below3(uint64_t id, uint32_t nb, int &X, int &Y, int &Z) {
         rem = r;
     }
     return false;
+}
+
+// ---------------------------------------------------------------- recursive
+// The recursive orthotope sets of Sec. III-B, mapped level by level in
+// O(log n) steps (the map the paper describes before setting it aside for its
+// cost in recursive calls).  They live in the paper's corner coordinates p
+// (p_1 + ... + p_m <= nb' - 1, the orthogonal corner at 0): the map of a simplex
+// of side s at relative origin c is the cube phi(w, c) of side s/2 at c,
+// followed by m maps of side s/2 at c + (s/2) e_d, one per axis (for m = 3 the
+// sides and the top of the cube), down to single blocks.  Blocks are numbered
+// depth first in that order: V(1) = 1, V(s) = (s/2)^m + m V(s/2), so that
+// V(nb') = nb'(nb'+1)/2 for m = 2 (every block inside) and (nb'^3 + 4 3^lg) / 5
+// for m = 3 (extra volume -> 1/5).  A corner point p is the tile
+// (p_1, p_1 + p_2[, p_1 + p_2 + p_3]) of T2 / T3 -- a unimodular shear, so a
+// cover of the corner simplex is a cover of the tile set; blocks whose last
+// coordinate reaches nb (outside the simplex, or past nb when nb' > nb) are
+// filtered.  Decoding walks down from the top: at side s the block is in the
+// cube if id < (s/2)^m, else in branch floor((id - (s/2)^m) / V(s/2)), found by
+// comparisons; V(s/2) = (V(s) - (s/2)^m) / m.
+SMX_HD uint64_t rec_blocks(int m, int lg) {
+    uint64_t v = 1;
+    for (int l = 1; l <= lg; ++l) v = (uint64_t(1) << (m * (l - 1))) + uint64_t(m) * v;
+    return v;
+}
+
+SMX_HD bool rec2(uint32_t id, int lg, int nb, uint32_t V, int &X, int &Y) {
+    uint32_t a = 0, b = 0;
+    for (int l = lg; l > 0; --l) {
+        const int h = l - 1;
+        const uint32_t cube = 1u << (2 * h);
+        if (id < cube) {
+            a += id & ((1u << h) - 1u);
+            b += id >> h;
+            break;
+        }
+        id -= cube;
+        const uint32_t vh = (V - cube) >> 1;
+        if (id < vh) {
+            a += 1u << h;
+        } else {
+            b += 1u << h;
+            id -= vh;
+        }
+        V = vh;
+    }
+    X = int(a);
+    Y = int(a + b);
+    return a + b < uint32_t(nb);
+}
+
+SMX_HD bool rec3(uint32_t id, int lg, int nb, uint32_t V, int &X, int &Y, int &Z) {
+    uint32_t a = 0, b = 0, c = 0;
+    for (int l = lg; l > 0; --l) {
+        const int h = l - 1;
+        const uint32_t cube = 1u << (3 * h);
+        if (id < cube) {
+            const uint32_t mask = (1u << h) - 1u;
+            a += id & mask;
+            b += (id >> h) & mask;
+            c += id >> (2 * h);
+            break;
+        }
+        id -= cube;
+        const uint32_t vh = (V - cube) / 3u;
+        if (id < vh) {
+            a += 1u << h;
+        } else if (id < 2 * vh) {
+            b += 1u << h;
+            id -= vh;
+        } else {
+            c += 1u << h;
+            id -= 2 * vh;
+        }
+        V = vh;
+    }
+    X = int(a);
+    Y = int(a + b);
+    Z = int(a + b + c);
+    return a + b + c < uint32_t(nb);
+}
+
+// One sub-orthotope of the recursive set on its own launch (MAP_CUBE): block
+// id of the cube of side 2^g.lg at corner origin (c0, c1[, c2]), x fastest.
+SMX_HD bool cube2(uint32_t id, const MapGeom &g, int &X, int &Y) {
+    const uint32_t a = uint32_t(g.c0) + (id & ((1u << g.lg) - 1u));
+    const uint32_t b = uint32_t(g.c1) + (id >> g.lg);
+    X = int(a);
+    Y = int(a + b);
+    return a + b < uint32_t(g.nb);
+}
+
+SMX_HD bool cube3(uint32_t id, const MapGeom &g, int &X, int &Y, int &Z) {
+    const uint32_t mask = (1u << g.lg) - 1u;
+    const uint32_t a = uint32_t(g.c0) + (id & mask);
+    const uint32_t b = uint32_t(g.c1) + ((id >> g.lg) & mask);
+    const uint32_t c = uint32_t(g.c2) + (id >> (2 * g.lg));
+    X = int(a);
+    Y = int(a + b);
+    Z = int(a + b + c);
+    return a + b + c < uint32_t(g.nb);
 }
 
 // ---------------------------------------------------------------- XCD order

@@ -142,7 +142,7 @@ static void go_packed(const MapGeom &g, const float *X, int64_t n, int64_t ldx, 
 int launch_triplet_packed(const MapGeom &g, const float *X, int64_t n, int64_t ldx, float nu, float *E,
                           unsigned long long *sslots, hipStream_t s) {
     prof_begin(K_TRIP_PACKED, s);
-    map_switch(int(g.map), [&](auto M) { go_packed<decltype(M)::value>(g, X, n, ldx, nu, E, sslots, s); });
+    for_each_launch(g, [&](auto M, const MapGeom &gg) { go_packed<decltype(M)::value>(gg, X, n, ldx, nu, E, sslots, s); });
     prof_end(K_TRIP_PACKED, s);
     return check_launch("triplet packed");
 }

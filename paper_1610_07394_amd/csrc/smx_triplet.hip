@@ -364,10 +364,10 @@ int launch_triplet(const MapGeom &g, const float *X, int64_t n, int64_t ldx, flo
                    double *G64, double *eslots, unsigned long long *sslots, hipStream_t s) {
     const int kid = grad ? K_TRIP_GRAD : K_TRIP_ENERGY;
     prof_begin(kid, s);
-    map_switch(int(g.map), [&](auto M) {
+    for_each_launch(g, [&](auto M, const MapGeom &gg) {
         constexpr int MAPK = decltype(M)::value;
-        if (grad) go_at<MAPK, true>(g, X, n, ldx, nu, G64, eslots, sslots, s);
-        else go_at<MAPK, false>(g, X, n, ldx, nu, G64, eslots, sslots, s);
+        if (grad) go_at<MAPK, true>(gg, X, n, ldx, nu, G64, eslots, sslots, s);
+        else go_at<MAPK, false>(gg, X, n, ldx, nu, G64, eslots, sslots, s);
     });
     prof_end(kid, s);
     return check_launch(grad ? "triplet energy+grad" : "triplet energy");
@@ -489,7 +489,7 @@ int launch_lj(const MapGeom &g, const float *X, int64_t n, int64_t ldx, float ep
               float rc2, double *G64, double *eslots, unsigned long long *sslots, hipStream_t s) {
     prof_begin(K_LJ, s);
     const float sig2 = sigma * sigma;
-    map_switch(int(g.map), [&](auto M) { go_lj<decltype(M)::value>(g, X, n, ldx, eps, sig2, rc2, G64, eslots, sslots, s); });
+    for_each_launch(g, [&](auto M, const MapGeom &gg) { go_lj<decltype(M)::value>(gg, X, n, ldx, eps, sig2, rc2, G64, eslots, sslots, s); });
     prof_end(K_LJ, s);
     return check_launch("lennard-jones");
 }

@@ -42,7 +42,7 @@ def test_version_and_volume():
 
 @pytest.mark.parametrize("m,n,rho", [(2, 1024, 16), (2, 65536, 64), (2, 1000, 16), (3, 2048, 32),
                                      (3, 8192, 32), (3, 100, 8), (2, 1, 16), (3, 5, 1)])
-@pytest.mark.parametrize("kind", ["lambda", "bbox", "linear", "lambda_below"])
+@pytest.mark.parametrize("kind", list(smx.MAPS))
 def test_parallel_blocks_match_oracle(m, n, rho, kind):
     nb = (n + rho - 1) // rho
     if m == 3 and kind == "bbox" and nb > 64:
@@ -53,7 +53,7 @@ def test_parallel_blocks_match_oracle(m, n, rho, kind):
 
 
 @pytest.mark.parametrize("nb", [1, 2, 3, 4, 7, 8, 16, 33, 64, 100, 512, 1024, 4096])
-@pytest.mark.parametrize("kind", ["lambda", "bbox", "linear", "lambda_below"])
+@pytest.mark.parametrize("kind", list(smx.MAPS))
 def test_host_map2_equals_oracle(nb, kind):
     if kind == "bbox" and nb > 1024:
         pytest.skip("bbox dump of nb^2 blocks checked at smaller nb")
@@ -63,7 +63,7 @@ def test_host_map2_equals_oracle(nb, kind):
 
 
 @pytest.mark.parametrize("nb", [1, 2, 3, 4, 5, 8, 16, 31, 64, 128, 256])
-@pytest.mark.parametrize("kind", ["lambda", "bbox", "linear", "lambda_below"])
+@pytest.mark.parametrize("kind", list(smx.MAPS))
 def test_host_map3_equals_oracle(nb, kind):
     if kind == "bbox" and nb > 64:
         pytest.skip("bbox dump of nb^3 blocks checked at smaller nb")
@@ -123,7 +123,8 @@ def test_validation_errors_before_any_device_work():
     # EDM argument checks
     assert L.smx_edm_packed(null, 10, 0, 3, 0, 0, null, null, 0, null, null) == 1
     assert L.smx_edm_packed(null, 10, 3, 2, 0, 0, null, null, 0, null, null) == 1
-    assert L.smx_edm_packed(null, 10, 3, 3, 5, 0, null, null, 0, null, null) == 1
+    assert L.smx_edm_packed(null, 10, 3, 3, 6, 0, null, null, 0, null, null) == 1  # internal map id
+    assert b"map" in L.smx_last_error()
     assert L.smx_edm_packed(null, 10, 3, 3, 0, 9, null, null, 0, null, null) == 1
     assert L.smx_edm_packed(null, 10, 3, 3, 0, 0, null, null, 0, null, null) == 1  # NULL X / D
     assert L.smx_edm_packed(ctypes.c_void_p(256), 10, 3, 3, 0, 1, ctypes.c_void_p(256), null, 0, null,

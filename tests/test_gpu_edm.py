@@ -30,7 +30,7 @@ import synth
 pytestmark = pytest.mark.gpu
 
 GOLD = os.path.join(os.path.dirname(__file__), "golden", "expected.json")
-KINDS = ["lambda", "bbox", "linear", "lambda_below"]
+KINDS = ["lambda", "bbox", "linear", "lambda_below", "recursive", "recursive_launch"]
 TOL = {"fp32": 1e-5, "bf16": 8e-3, "split_bf16": 1e-4}
 
 

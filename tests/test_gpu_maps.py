@@ -15,7 +15,7 @@ from oracle import maps as omaps
 pytestmark = pytest.mark.gpu
 
 GOLD = os.path.join(os.path.dirname(__file__), "golden", "expected.json")
-KINDS = ["lambda", "bbox", "linear", "lambda_below"]
+KINDS = ["lambda", "bbox", "linear", "lambda_below", "recursive", "recursive_launch"]
 
 
 def _gold():

@@ -17,7 +17,7 @@ import synth
 
 pytestmark = pytest.mark.gpu
 
-KINDS = ["lambda", "bbox", "linear", "lambda_below"]
+KINDS = ["lambda", "bbox", "linear", "lambda_below", "recursive", "recursive_launch"]
 TOL = 1e-5
 
 

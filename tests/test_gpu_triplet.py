@@ -22,7 +22,7 @@ import synth
 pytestmark = pytest.mark.gpu
 
 GOLD = os.path.join(os.path.dirname(__file__), "golden", "expected.json")
-KINDS = ["lambda", "bbox", "linear", "lambda_below"]
+KINDS = ["lambda", "bbox", "linear", "lambda_below", "recursive", "recursive_launch"]
 AT = smx.Pot(nu=1.0, at=True, lj=False)
 ATLJ = smx.Pot(nu=1.0, at=True, lj=True, eps=1.0, sigma=1.0, rc=3.0)
 
