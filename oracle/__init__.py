@@ -171,7 +171,7 @@ def checksum_range(v: int) -> int:
     return int(lib().orc_checksum_range(v))
 
 
-KIND = {"pairs_le": 0, "pairs_lt": 1, "triplets_le": 2, "triplets_lt": 3}
+KIND = {"pairs_le": 0, "pairs_lt": 1, "triplets_le": 2, "triplets_lt": 3, "quads_le": 4, "quads_lt": 5}
 
 
 def checksum_walk(kind: str, n: int) -> tuple[int, int]:

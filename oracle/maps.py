@@ -7,6 +7,7 @@ sets:
 
   T2 = {(x, y): 0 <= x <= y < nb}
   T3 = {(x, y, z): 0 <= x <= y <= z < nb}
+  T4 = {(x1, x2, x3, x4): 0 <= x1 <= x2 <= x3 <= x4 < nb}
 
 Block linearisation (the layout of a tile dump): x varies fastest, then y,
 then z.  For the 3-simplex lambda map the linear index first runs over Pi3 and
@@ -308,6 +309,134 @@ def recursive_tiles(m: int, nb: int) -> np.ndarray:
     return t
 
 
+# --------------------------------------------------------------------------
+# 4-simplex (Sec. III-D: the recursive set of orthotopes for general m with
+# r = 1/2, beta = 2, V = (n^4 - n) / 14).  The paper gives the set and its
+# volume, not a map; the map written out here is this implementation's
+# reading.  Target T4 = {x1 <= x2 <= x3 <= x4 < nb}, split as
+#   T4s = {x1 <= x2 <= x3 < x4}  (C(nb+2, 4) tiles, the paper's V(Delta_{n-1}))
+#   plane {x3 = x4}              (a copy of T3, covered by a lambda3 grid over nb,
+#                                 tile (X, Y, Z) -> (X, Y, Z, Z)).
+# T4s splits over the binary recursion on [0, nb'): a tuple belongs to the node
+# (offset o, size 2b) where x1 and x4 first fall on different halves,
+# L = [o, o+b) and H = [o+b, o+2b).  The node's cross region is
+#   R3 = {x1 <= x2 <= x3 in L, x4 in H},
+#   R2 = {x1 <= x2 in L, x3 < x4 in H},
+#   R1 = {x1 in L, x2 <= x3 < x4 in H},
+# b^2 (b+1) (7b-1) / 12 tiles in all, never more than b^4.  Each node owns one
+# b^4 orthotope of blocks (level l = 0, 1, ... has 2^l nodes of side
+# b = nb'/2^(l+1), so the orthotopes add up to (nb'^4 - nb') / 14): its first
+# blocks list R3, then R2, then R1, and the rest are filtered.  Listing order
+# inside a region: R3 by the sorted triple (by x3, then x2, then x1), x4
+# fastest; R2 by the pair in L (by x2, then x1), then the pair in H (by x4,
+# then x3) fastest; R1 by the triple in H (by x4, then x3, then x2), x1
+# fastest.  Blocks: levels in order, nodes by offset, then the plane grid.
+def _sorted_tuples(b: int, r: int, strict_last: bool) -> list:
+    """Non-decreasing r-tuples over [0, b) (the last step strict when asked),
+    ordered by the last coordinate, then the one before, ... (colex)."""
+    out = []
+
+    def rec(prefix_rev, k, hi):
+        # prefix_rev holds the chosen coordinates from the last one down
+        if k == 0:
+            out.append(tuple(reversed(prefix_rev)))
+            return
+        for v in range(hi):
+            rec(prefix_rev + [v], k - 1, v + 1)
+
+    if strict_last:
+        for last in range(b):
+            sub = []
+
+            def rec2(prefix_rev, k, hi):
+                if k == 0:
+                    sub.append(tuple(reversed(prefix_rev)) + (last,))
+                    return
+                for v in range(hi):
+                    rec2(prefix_rev + [v], k - 1, v + 1)
+            rec2([], r - 1, last)
+            # colex order on the leading coordinates within one last value
+            sub.sort(key=lambda t: tuple(reversed(t[:-1])))
+            out.extend(sub)
+        return out
+    rec([], r, b)
+    out.sort(key=lambda t: tuple(reversed(t)))
+    return out
+
+
+def lambda4_main_tiles(nb: int) -> np.ndarray:
+    nbp = next_pow2(nb)
+    rows = []
+    b = nbp // 2
+    nodes = 1
+    while b >= 1:
+        r3 = _sorted_tuples(b, 3, False)
+        l2 = _sorted_tuples(b, 2, False)
+        h2 = _sorted_tuples(b, 2, True)
+        h3 = _sorted_tuples(b, 3, True)
+        for q in range(nodes):
+            o = 2 * q * b
+            cross = []
+            for (a, c, d) in r3:
+                for e in range(b):
+                    cross.append((o + a, o + c, o + d, o + b + e))
+            for (a, c) in l2:
+                for (d, e) in h2:
+                    cross.append((o + a, o + c, o + b + d, o + b + e))
+            for (c, d, e) in h3:
+                for a in range(b):
+                    cross.append((o + a, o + b + c, o + b + d, o + b + e))
+            assert len(cross) <= b ** 4
+            cross += [(FILTERED,) * 4] * (b ** 4 - len(cross))
+            rows += cross
+        b //= 2
+        nodes *= 2
+    t = np.array(rows, dtype=np.int64).reshape(-1, 4)
+    t[t[:, 3] >= nb] = FILTERED
+    return t
+
+
+def lambda4_tiles(nb: int) -> np.ndarray:
+    main = lambda4_main_tiles(nb)
+    p3 = lambda3_tiles(nb)
+    plane = np.full((p3.shape[0], 4), FILTERED, dtype=np.int64)
+    ok = p3[:, 0] >= 0
+    plane[ok, :3] = p3[ok]
+    plane[ok, 3] = p3[ok, 2]
+    return np.concatenate([main, plane], axis=0)
+
+
+def bbox4_tiles(nb: int) -> np.ndarray:
+    idx = np.arange(nb ** 4, dtype=np.int64)
+    t = np.stack([idx // nb ** d % nb for d in range(4)], axis=1)
+    bad = (t[:, 0] > t[:, 1]) | (t[:, 1] > t[:, 2]) | (t[:, 2] > t[:, 3])
+    t[bad] = FILTERED
+    return t
+
+
+def linear4_tiles(nb: int) -> np.ndarray:
+    """Block k = the k-th tile of T4 listed by x4, then x3, x2, x1 (exact search
+    over integer tables of the simplicial numbers)."""
+    w = np.arange(nb + 1, dtype=np.int64)
+    pen = w * (w + 1) * (w + 2) * (w + 3) // 24   # tiles with a smaller x4
+    tet = w * (w + 1) * (w + 2) // 6
+    tri = w * (w + 1) // 2
+    k = np.arange(pen[nb], dtype=np.int64)
+    x4 = np.searchsorted(pen, k, side="right") - 1
+    r = k - pen[x4]
+    x3 = np.searchsorted(tet, r, side="right") - 1
+    r = r - tet[x3]
+    x2 = np.searchsorted(tri, r, side="right") - 1
+    x1 = r - tri[x2]
+    return np.stack([x1, x2, x3, x4], axis=1)
+
+
+def lambda4_blocks(nb: int) -> int:
+    """|Pi4| = (nb'^4 - nb') / 14 orthotope blocks + the lambda3 plane grid."""
+    nbp = next_pow2(nb)
+    return (nbp ** 4 - nbp) // 14 + lambda3_tiles(nb).shape[0]
+
+
 def recursive_sub_maps(m: int, nb: int) -> int:
     """Number of sub-orthotopes (map calls, one launch each) of the recursive
     set of side next_pow2(nb): the cube of every recursion node plus the
@@ -330,6 +459,8 @@ def tiles(m: int, nb: int, kind: str) -> np.ndarray:
     if m == 3:
         return {"lambda": lambda3_tiles, "bbox": bbox3_tiles, "linear": linear3_tiles,
                 "lambda_below": below3_tiles}[kind](nb)
+    if m == 4:
+        return {"lambda": lambda4_tiles, "bbox": bbox4_tiles, "linear": linear4_tiles}[kind](nb)
     raise ValueError(m)
 
 
@@ -337,6 +468,8 @@ def target_tiles(m: int, nb: int) -> set:
     """The target tile set, by nested loops."""
     if m == 2:
         return {(x, y) for y in range(nb) for x in range(y + 1)}
+    if m == 4:
+        return {(x, y, z, w) for w in range(nb) for z in range(w + 1) for y in range(z + 1) for x in range(y + 1)}
     return {(x, y, z) for z in range(nb) for y in range(z + 1) for x in range(y + 1)}
 
 

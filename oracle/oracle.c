@@ -334,6 +334,8 @@ void orc_lj_grad(const float *X, int64_t n, int64_t ldx, double eps, double sigm
  *   pairs i<j      : id = j(j-1)/2 + i
  *   triplets i<=j<=k: id = k(k+1)(k+2)/6 + j(j+1)/2 + i
  *   triplets i<j<k : id = k(k-1)(k-2)/6 + j(j-1)/2 + i
+ *   quadruplets i<=j<=k<=l: id = l(l+1)(l+2)(l+3)/24 + k(k+1)(k+2)/6 + j(j+1)/2 + i
+ *   quadruplets i<j<k<l   : id = l(l-1)(l-2)(l-3)/24 + k(k-1)(k-2)/6 + j(j-1)/2 + i
  */
 static uint64_t orc_splitmix64(uint64_t x)
 {
@@ -364,8 +366,9 @@ uint64_t orc_checksum_range(uint64_t v)
 }
 
 /* Checksum of the elements a nested-loop walk visits: kind 0 = pairs i<=j,
- * 1 = pairs i<j, 2 = triplets i<=j<=k, 3 = triplets i<j<k.  This enumerates
- * the elements and their ids directly (no use of the bijection property).   */
+ * 1 = pairs i<j, 2 = triplets i<=j<=k, 3 = triplets i<j<k, 4 = quadruplets
+ * i<=j<=k<=l, 5 = quadruplets i<j<k<l.  This enumerates the elements and their
+ * ids directly (no use of the bijection property).                           */
 uint64_t orc_checksum_walk(int kind, int64_t n, int64_t *count)
 {
     uint64_t s = 0;
@@ -389,13 +392,31 @@ uint64_t orc_checksum_walk(int kind, int64_t n, int64_t *count)
                     s += orc_splitmix64((uint64_t)((k * (k + 1) * (k + 2)) / 6 + (j * (j + 1)) / 2 + i));
                     ++c;
                 }
-    } else {
+    } else if (kind == 3) {
         for (int64_t i = 0; i < n; ++i)
             for (int64_t j = i + 1; j < n; ++j)
                 for (int64_t k = j + 1; k < n; ++k) {
                     s += orc_splitmix64((uint64_t)((k * (k - 1) * (k - 2)) / 6 + (j * (j - 1)) / 2 + i));
                     ++c;
                 }
+    } else if (kind == 4) {
+        for (int64_t i = 0; i < n; ++i)
+            for (int64_t j = i; j < n; ++j)
+                for (int64_t k = j; k < n; ++k)
+                    for (int64_t l = k; l < n; ++l) {
+                        s += orc_splitmix64((uint64_t)((l * (l + 1) * (l + 2) * (l + 3)) / 24 +
+                                                       (k * (k + 1) * (k + 2)) / 6 + (j * (j + 1)) / 2 + i));
+                        ++c;
+                    }
+    } else {
+        for (int64_t i = 0; i < n; ++i)
+            for (int64_t j = i + 1; j < n; ++j)
+                for (int64_t k = j + 1; k < n; ++k)
+                    for (int64_t l = k + 1; l < n; ++l) {
+                        s += orc_splitmix64((uint64_t)((l * (l - 1) * (l - 2) * (l - 3)) / 24 +
+                                                       (k * (k - 1) * (k - 2)) / 6 + (j * (j - 1)) / 2 + i));
+                        ++c;
+                    }
     }
     if (count) *count = c;
     return s;

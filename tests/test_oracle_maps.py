@@ -339,3 +339,75 @@ def test_recursive_first_blocks_are_the_main_cube(m):
     np.testing.assert_array_equal(p[inside], q[inside])
     nxt = t[h ** m]
     assert tuple(nxt) == ((h, h) if m == 2 else (h, h, h))
+
+
+# --------------------------------------------------------------------------
+# 4-simplex: the r = 1/2, beta = 2 recursive set of Sec. III-D and the lambda4
+# reading built on it.
+def test_lambda4_golden_nb4():
+    g = _read_golden("lambda4_nb4.txt")
+    t = maps.lambda4_main_tiles(4)
+    np.testing.assert_array_equal(g[:, 0], np.arange(18))
+    np.testing.assert_array_equal(t, g[:, 1:])
+
+
+@pytest.mark.parametrize("kind", ["lambda", "bbox", "linear", "recursive"])
+@pytest.mark.parametrize("nb", [1, 2, 3, 4, 5, 7, 8, 9, 16, 17])
+def test_map4_bijection(kind, nb):
+    ok, msg = maps.check_bijection(maps.tiles(4, nb, kind), 4, nb)
+    assert ok, msg
+
+
+@pytest.mark.parametrize("k", range(0, 6))
+def test_lambda4_orthotopes_follow_recursive_set(k):
+    """The orthotope part has the paper's volume V(S^4_n) = (n^4 - n)/14 (the
+    recursion (n/2)^4 + 2 V(n/2), built by _vol_rec) and covers T4s =
+    {x1 <= x2 <= x3 < x4}, whose C(n+2, 4) = (n-1)n(n+1)(n+2)/24 tiles are the
+    paper's V(Delta_{n-1}); each node's cross region has b^2 (b+1)(7b-1)/12 tiles."""
+    n = 2 ** k
+    main = maps.lambda4_main_tiles(n)
+    assert main.shape[0] == _vol_rec(n, 4, 2) == (n ** 4 - n) // 14
+    valid = main[main[:, 0] >= 0]
+    assert valid.shape[0] == comb(n + 2, 4) == (n - 1) * n * (n + 1) * (n + 2) // 24
+    assert (valid[:, 2] < valid[:, 3]).all()
+    # per level: 2^l nodes, each b^4 blocks of which the cross region maps
+    off, b, nodes = 0, n // 2, 1
+    while b >= 1:
+        cross = b * b * (b + 1) * (7 * b - 1) // 12
+        assert cross <= b ** 4
+        for q in range(nodes):
+            blk = main[off:off + b ** 4]
+            assert (blk[:cross, 0] >= 0).all() and (blk[cross:] == maps.FILTERED).all()
+            o = 2 * q * b
+            assert (blk[:cross, 0] >= o).all() and (blk[:cross, 0] < o + b).all()
+            assert (blk[:cross, 3] >= o + b).all() and (blk[:cross, 3] < o + 2 * b).all()
+            off += b ** 4
+        b //= 2
+        nodes *= 2
+
+
+def test_lambda4_extra_volume():
+    """Sec. III-D: with r = 1/2, beta = 2 the m = 4 set exceeds the simplex by a
+    fraction tending to 4!/(2^4 - 2) - 1 = 5/7; the lambda4 blocks (orthotopes +
+    plane grid) over the tiles of T4 approach the same limit from below."""
+    prev = 0.0
+    for k in range(1, 7):
+        n = 2 ** k
+        a = maps.lambda4_blocks(n) / comb(n + 3, 4) - 1
+        assert prev <= a < Fraction(5, 7)
+        prev = a
+    assert prev > 0.6
+    assert Fraction(factorial(4), 2 ** 4 - 2) - 1 == Fraction(5, 7)
+
+
+def test_linear4_matches_nested_loops():
+    nb = 12
+    want = [(x, y, z, w) for w in range(nb) for z in range(w + 1) for y in range(z + 1) for x in range(y + 1)]
+    np.testing.assert_array_equal(maps.linear4_tiles(nb), np.array(want, dtype=np.int64))
+
+
+@pytest.mark.parametrize("k", range(0, 6))
+def test_recursive4_counts(k):
+    n = 2 ** k
+    assert maps.recursive_tiles(4, n).shape[0] == _vol_rec(n, 4, 4) + 4 ** k
+    assert maps.recursive_sub_maps(4, n) == (4 ** (k + 1) - 1) // 3

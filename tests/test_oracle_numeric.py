@@ -245,7 +245,8 @@ def test_splitmix64_published_outputs():
 
 
 @pytest.mark.parametrize("kind,m,strict", [("pairs_le", 2, False), ("pairs_lt", 2, True),
-                                           ("triplets_le", 3, False), ("triplets_lt", 3, True)])
+                                           ("triplets_le", 3, False), ("triplets_lt", 3, True),
+                                           ("quads_le", 4, False), ("quads_lt", 4, True)])
 @pytest.mark.parametrize("n", [0, 1, 2, 3, 17, 40])
 def test_checksum_ids_are_bijective(kind, m, strict, n):
     s, c = oracle.checksum_walk(kind, n)
@@ -263,3 +264,11 @@ def test_checksum_walk_pure_python():
             for k in range(j, n):
                 s = (s + oracle.mix64(k * (k + 1) * (k + 2) // 6 + j * (j + 1) // 2 + i)) % M
     assert oracle.checksum_walk("triplets_le", n)[0] == s
+    s = 0
+    for i in range(n):
+        for j in range(i + 1, n):
+            for k in range(j + 1, n):
+                for l in range(k + 1, n):
+                    s = (s + oracle.mix64(l * (l - 1) * (l - 2) * (l - 3) // 24 + k * (k - 1) * (k - 2) // 6
+                                          + j * (j - 1) // 2 + i)) % M
+    assert oracle.checksum_walk("quads_lt", n)[0] == s
