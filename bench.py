@@ -44,6 +44,7 @@ AT_SOURCES = ("smx_triplet.hip", "smx_device.h", "smx_maps.h")
 N_EDM, D_EDM = 65536, 64
 N_GRAM, D_GRAM = 32768, 512
 N_AT = 8192
+N_MAP4 = 1024  # 4-simplex map-only comparison: 8^4-element tiles, nb = 128
 
 
 def parse():
@@ -288,10 +289,12 @@ def main():
         # count, so the time is the map plus the launched blocks alone.
         mo = {}
         for kind in ("lambda", "bbox", "linear", "lambda_below", "recursive", "recursive_launch"):
-            for m, n, rho in ((2, N_EDM, 16), (3, N_AT, 8)):
-                visit = smx.simplex_map2 if m == 2 else smx.simplex_map3
-                runs = (("visit", lambda: visit(n, rho, kind, strict=(m == 3), tiles=False)),
-                        ("count", lambda: smx.simplex_count(m, n, rho, kind, strict=(m == 3))))
+            for m, n, rho in ((2, N_EDM, 16), (3, N_AT, 8), (4, N_MAP4, 8)):
+                if m == 4 and kind == "lambda_below":
+                    continue  # not defined for the 4-simplex
+                visit = {2: smx.simplex_map2, 3: smx.simplex_map3, 4: smx.simplex_map4}[m]
+                runs = (("visit", lambda: visit(n, rho, kind, strict=(m >= 3), tiles=False)),
+                        ("count", lambda: smx.simplex_count(m, n, rho, kind, strict=(m >= 3))))
                 for what, fn in runs:
                     fn()
                     torch.cuda.synchronize()
@@ -299,7 +302,7 @@ def main():
                     smx.profile_reset()
                     for _ in range(3):
                         fn()
-                    ms, c = smx.profile_read("map2" if m == 2 else "map3")
+                    ms, c = smx.profile_read(f"map{m}")
                     smx.profile_enable(False)
                     mo[f"{what}{m}_{kind}_n{n}_rho{rho}_ms"] = ms / c
         compare["map_only"] = mo

@@ -117,14 +117,15 @@ const char *smx_version(void);
 const char *smx_last_error(void);
 
 /* Number of simplex elements: C(n+m-1, m) (paper eq. (2)) or C(n, m) when
- * strict != 0, for m in {2, 3}.  Host only.  -1 on bad arguments or overflow. */
+ * strict != 0, for m in {2, 3, 4}.  Host only.  -1 on bad arguments or overflow. */
 int64_t smx_volume(int m, int64_t n, int strict);
 
 /* Number of blocks the map launches for n elements per dimension and tile
- * edge rho (the |Pi| of the paper, in blocks), m in {2, 3}.  For
+ * edge rho (the |Pi| of the paper, in blocks), m in {2, 3, 4}.  For
  * SMX_MAP_LAMBDA and m = 3 this is |Pi3| plus the lambda2 grid of the plane
- * Y = Z.  It sizes the tile dump of smx_simplex_map2/3.  Host only; -1 on bad
- * arguments or overflow. */
+ * Y = Z; for m = 4, the (nb'^4 - nb')/14 orthotope blocks plus the lambda3
+ * grid of the plane X3 = X4.  It sizes the tile dump of smx_simplex_map2/3/4.
+ * Host only; -1 on bad arguments or overflow. */
 int64_t smx_parallel_blocks(int m, int64_t n, int rho, int map);
 
 /* The tiles of launched blocks first .. first+count-1, written to host memory
@@ -163,10 +164,32 @@ int smx_simplex_map2(int64_t n, int rho, int map, int strict, int32_t *d_tiles,
 int smx_simplex_map3(int64_t n, int rho, int map, int strict, int32_t *d_tiles,
                      int64_t *d_stats, void *d_ws, size_t ws_bytes, void *stream);
 
+/* Map dump over the 4-simplex (Sec. III-D), as smx_simplex_map2 with
+ * quadruplets i <= j <= k <= l (or i < j < k < l when strict != 0), element id
+ * l(l+1)(l+2)(l+3)/24 + k(k+1)(k+2)/6 + j(j+1)/2 + i (strict: l(l-1)(l-2)(l-3)/24
+ * + k(k-1)(k-2)/6 + j(j-1)/2 + i); rho a power of two in [1, 16].  d_tiles is
+ * int32[smx_parallel_blocks(4, n, rho, map)][4], tiles X1 <= X2 <= X3 <= X4.
+ * Maps: LAMBDA is the 4-simplex map built on the paper's r = 1/2, beta = 2
+ * recursive set (the paper gives the set and its volume (n^4 - n)/14, not a
+ * map): T4 splits into T4s = {X1 <= X2 <= X3 < X4} and the plane X3 = X4.  A
+ * node of the binary recursion on [0, nb') (offset o, halves L and H of side b)
+ * owns one b^4 orthotope of blocks whose leading blocks list its cross region
+ * -- {X1<=X2<=X3 in L, X4 in H}, {X1<=X2 in L, X3<X4 in H}, {X1 in L,
+ * X2<=X3<X4 in H}, b^2(b+1)(7b-1)/12 tiles, by exact-root unranking -- and
+ * whose other blocks are filtered (5/7 extra in the limit, as the paper
+ * states).  Block order: levels (b = nb'/2, nb'/4, ...), nodes by offset, then
+ * a lambda3 grid over nb whose tile (X, Y, Z) becomes (X, Y, Z, Z).  BBOX is
+ * an nb^4 1-D grid decoded with divisions (there is no 4-D hardware grid);
+ * LINEAR lists T4 by X4, X3, X2, X1 (FP32 fourth root plus exact fix-up);
+ * RECURSIVE / RECURSIVE_LAUNCH are the corner-coordinate recursion with four
+ * branches.  LAMBDA_BELOW is not defined for m = 4 (SMX_EUNSUPPORTED). */
+int smx_simplex_map4(int64_t n, int rho, int map, int strict, int32_t *d_tiles,
+                     int64_t *d_stats, void *d_ws, size_t ws_bytes, void *stream);
+
 /* Parallel space only (paper Sec. I and III: the cost of a map is the map plus
  * the blocks it launches).  Launches the parallel space of `map` for m in
- * {2, 3}, n elements per dimension and tile edge rho (power of two, <= 1024
- * for m = 2, <= 64 for m = 3) with 256-thread blocks; each block that maps to
+ * {2, 3, 4}, n elements per dimension and tile edge rho (power of two, <= 1024
+ * for m = 2, <= 64 for m = 3, <= 16 for m = 4) with 256-thread blocks; each block that maps to
  * a tile adds the number of simplex elements of that tile (le, or lt when
  * strict != 0), obtained in closed form, and filtered blocks exit at once.
  *   d_stats  int64[4]: [0] elements (= smx_volume(m, n, strict)), [1] 0,
@@ -247,7 +270,7 @@ int smx_scale_grad(const float *d_G, int64_t n, const double *d_gradE, float *d_
  * events on its own stream.  smx_profile_read synchronises on those events and
  * returns the summed duration (ms) and launch count of kernel `kernel_id`
  * (0 map2, 1 map3, 2 edm diff, 3 edm gram, 4 gram prep, 5 triplet energy,
- * 6 triplet grad, 7 lj, 8 finalize, 9 triplet packed) since the last reset; it
+ * 6 triplet grad, 7 lj, 8 finalize, 9 triplet packed, 10 map4) since the last reset; it
  * returns SMX_EINVAL
  * for an unknown id.  smx_profile_reset clears the totals.  Host only. */
 int smx_profile_enable(int on);

@@ -16,7 +16,7 @@ import torch
 
 __all__ = [
     "MAPS", "PRECS", "SmxError", "Pot", "lib", "volume", "parallel_blocks", "map_tiles_host",
-    "workspace_bytes", "simplex_map2", "simplex_map3", "simplex_count", "triplet_packed", "edm_packed", "triplet_energy",
+    "workspace_bytes", "simplex_map2", "simplex_map3", "simplex_map4", "simplex_count", "triplet_packed", "edm_packed", "triplet_energy",
     "triplet_energy_grad", "triplet_energy_backward", "TripletEnergy", "profile_enable",
     "profile_reset", "profile_read", "KERNELS",
 ]
@@ -27,7 +27,7 @@ LIB_PATH = os.path.join(_HERE, "libsmx.so")
 MAPS = {"lambda": 0, "bbox": 1, "linear": 2, "lambda_below": 3, "recursive": 4, "recursive_launch": 5}
 PRECS = {"fp32": 0, "bf16": 1, "split_bf16": 2}
 KERNELS = {"map2": 0, "map3": 1, "edm_diff": 2, "edm_gram": 3, "gram_prep": 4,
-           "triplet_energy": 5, "triplet_grad": 6, "lj": 7, "finalize": 8, "triplet_packed": 9}
+           "triplet_energy": 5, "triplet_grad": 6, "lj": 7, "finalize": 8, "triplet_packed": 9, "map4": 10}
 
 _i32, _i64, _sz, _vp, _dbl = ctypes.c_int, ctypes.c_int64, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_double
 
@@ -74,7 +74,7 @@ def lib():
         L.smx_map_tiles_host.argtypes = [_i32, _i64, _i32, _i32, _i64, _i64, _vp]
         L.smx_workspace_bytes.argtypes = [_i32, _i64, _i64, _i32, _i32]
         L.smx_workspace_bytes.restype = _sz
-        for name in ("smx_simplex_map2", "smx_simplex_map3"):
+        for name in ("smx_simplex_map2", "smx_simplex_map3", "smx_simplex_map4"):
             getattr(L, name).argtypes = [_i64, _i32, _i32, _i32, _vp, _vp, _vp, _sz, _vp]
         L.smx_simplex_count.argtypes = [_i32, _i64, _i32, _i32, _i32, _vp, _vp, _sz, _vp]
         L.smx_triplet_packed.argtypes = [_vp, _i64, _i64, _dbl, _i32, _vp, _vp, _sz, _vp, _vp]
@@ -165,7 +165,7 @@ def _simplex_map(m: int, n: int, rho: int, map, strict: bool, tiles: bool, stats
     t = torch.empty((g, m), dtype=torch.int32, device=device) if tiles else None
     s = torch.zeros(4, dtype=torch.int64, device=device) if stats else None
     ws = _ws(workspace_bytes(0, n), device) if stats else None
-    fn = lib().smx_simplex_map2 if m == 2 else lib().smx_simplex_map3
+    fn = {2: lib().smx_simplex_map2, 3: lib().smx_simplex_map3, 4: lib().smx_simplex_map4}[m]
     _check(fn(n, rho, _map(map), int(strict), _ptr(t), _ptr(s), _ptr(ws), 0 if ws is None else ws.numel(),
               _stream()))
     return t, s
@@ -179,6 +179,11 @@ def simplex_map2(n: int, rho: int, map="lambda", strict=False, tiles=True, stats
 def simplex_map3(n: int, rho: int, map="lambda", strict=False, tiles=True, stats=True, device="cuda"):
     """Run the 3-simplex parallel space; returns (tiles int32 [G, 3] | None, stats int64 [4] | None)."""
     return _simplex_map(3, n, rho, map, strict, tiles, stats, device)
+
+
+def simplex_map4(n: int, rho: int, map="lambda", strict=False, tiles=True, stats=True, device="cuda"):
+    """Run the 4-simplex parallel space; returns (tiles int32 [G, 4] | None, stats int64 [4] | None)."""
+    return _simplex_map(4, n, rho, map, strict, tiles, stats, device)
 
 
 def simplex_count(m: int, n: int, rho: int, map="lambda", strict=False, device="cuda"):

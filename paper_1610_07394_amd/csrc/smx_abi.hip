@@ -15,12 +15,15 @@
 namespace smx {
 
 static thread_local char g_err[512] = "";
+// Code of the last fail() on this thread: what a failed make_geom reported.
+static thread_local int g_status = SMX_OK;
 
 int fail(int code, const char *fmt, ...) {
     va_list ap;
     va_start(ap, fmt);
     vsnprintf(g_err, sizeof(g_err), fmt, ap);
     va_end(ap);
+    g_status = code;
     return code;
 }
 
@@ -90,7 +93,25 @@ bool make_geom(int m, int64_t nb, int map, MapGeom &g) {
     g.map = uint32_t(map);
     g.dim = m;
     const uint64_t u = uint64_t(nb);
-    if (map == MAP_REC || map == MAP_REC_LAUNCH) {
+    if (m == 4) {
+        if (map == MAP_BELOW)
+            return fail(SMX_EUNSUPPORTED, "the from-below map is defined for m = 2 and 3 only"), false;
+        if (nb > 65535) return fail(SMX_EOVERFLOW, "grid too large (nb = %lld)", (long long)nb), false;
+        if (map == MAP_LAMBDA) {
+            g.lg = ceil_log2_u64(u);
+            if (g.lg > 8) return fail(SMX_EOVERFLOW, "lambda4 grid too large (nb = %lld)", (long long)nb), false;
+            g.main = uint32_t(lambda4_main_blocks(g.lg));
+            g.G = g.main + lambda3_main_blocks(g.lg) + lambda2_blocks(g.lg);
+        } else if (map == MAP_REC || map == MAP_REC_LAUNCH) {
+            g.lg = ceil_log2_u64(u);
+            if (g.lg > 15) return fail(SMX_EOVERFLOW, "recursive grid too large (nb = %lld)", (long long)nb), false;
+            g.G = rec_blocks(4, g.lg);
+        } else if (map == MAP_BBOX) {
+            g.G = u * u * u * u;
+        } else {
+            g.G = u * (u + 1) * (u + 2) * (u + 3) / 24;
+        }
+    } else if (map == MAP_REC || map == MAP_REC_LAUNCH) {
         g.lg = ceil_log2_u64(u);
         if (g.lg > 20) return fail(SMX_EOVERFLOW, "recursive grid too large (nb = %lld)", (long long)nb), false;
         g.G = rec_blocks(m, g.lg);
@@ -121,8 +142,12 @@ bool make_geom(int m, int64_t nb, int map, MapGeom &g) {
     return true;
 }
 
+// Largest tile edge per dimension: the element-visiting kernels loop over
+// rho^m elements per block.
+static int max_rho(int m) { return m == 2 ? 1024 : m == 3 ? 64 : 16; }
+
 static int check_common(int m, int64_t n, int rho, int map, int maxrho) {
-    if (m != 2 && m != 3) return fail(SMX_EINVAL, "m must be 2 or 3 (got %d)", m);
+    if (m < 2 || m > 4) return fail(SMX_EINVAL, "m must be 2, 3 or 4 (got %d)", m);
     if (n < 0) return fail(SMX_EINVAL, "n must be >= 0 (got %lld)", (long long)n);
     if (n > kMaxN) return fail(SMX_EOVERFLOW, "n = %lld exceeds 2^31 - 1", (long long)n);
     if (!pow2(rho) || rho > maxrho) return fail(SMX_EINVAL, "rho must be a power of two in [1, %d] (got %d)", maxrho, rho);
@@ -180,18 +205,19 @@ const char *smx_version(void) { return "smx 0.1 (gfx950)"; }
 const char *smx_last_error(void) { return g_err; }
 
 int64_t smx_volume(int m, int64_t n, int strict) {
-    if ((m != 2 && m != 3) || n < 0 || n > kMaxN) return -1;
+    if (m < 2 || m > 4 || n < 0 || n > kMaxN) return -1;
     const __int128 a = n, b = strict ? n - 1 : n + 1;
     __int128 v;
     if (m == 2) v = a * b / 2;
-    else v = strict ? a * (n - 1) * (n - 2) / 6 : a * (n + 1) * (n + 2) / 6;
+    else if (m == 3) v = strict ? a * (n - 1) * (n - 2) / 6 : a * (n + 1) * (n + 2) / 6;
+    else v = strict ? a * (n - 1) * (n - 2) * (n - 3) / 24 : a * (n + 1) * (n + 2) * (n + 3) / 24;
     if (v < 0) v = 0;
     if (v > (__int128)INT64_MAX) return -1;
     return int64_t(v);
 }
 
 int64_t smx_parallel_blocks(int m, int64_t n, int rho, int map) {
-    if (check_common(m, n, rho, map, m == 2 ? 1024 : 64) != SMX_OK) return -1;
+    if (check_common(m, n, rho, map, max_rho(m)) != SMX_OK) return -1;
     if (n == 0) return 0;
     MapGeom g;
     if (!make_geom(m, (n + rho - 1) / rho, map, g)) return -1;
@@ -211,19 +237,33 @@ size_t smx_workspace_bytes(int op, int64_t n, int64_t d, int prec, int map) {
 }
 
 int smx_map_tiles_host(int m, int64_t n, int rho, int map, int64_t first, int64_t count, int32_t *tiles) {
-    int rc = check_common(m, n, rho, map, m == 2 ? 1024 : 64);
+    int rc = check_common(m, n, rho, map, max_rho(m));
     if (rc != SMX_OK) return rc;
     if (count < 0 || first < 0) return fail(SMX_EINVAL, "negative block range");
     if (count == 0) return SMX_OK;
     if (tiles == nullptr) return fail(SMX_EINVAL, "tiles is NULL");
     MapGeom g;
-    if (n == 0 || !make_geom(m, (n + rho - 1) / rho, map, g)) return n == 0 ? fail(SMX_EINVAL, "n = 0 launches no blocks") : SMX_EOVERFLOW;
+    if (n == 0) return fail(SMX_EINVAL, "n = 0 launches no blocks");
+    if (!make_geom(m, (n + rho - 1) / rho, map, g)) return g_status;
     if (uint64_t(first) + uint64_t(count) > g.G) return fail(SMX_EINVAL, "block range past the parallel space");
     for (uint64_t b = uint64_t(first); b < uint64_t(first + count); ++b) {
         int X = -1, Y = -1, Z = -1;
         int32_t *o = tiles + (b - uint64_t(first)) * m;
         bool ok;
-        if (m == 2) {
+        if (m == 4) {
+            int T[4] = {-1, -1, -1, -1};
+            if (map == MAP_LAMBDA) ok = lambda4(uint32_t(b), g.lg, g.nb, g.main, T);
+            else if (map == MAP_BBOX) {
+                uint64_t r = b;
+                for (int d = 0; d < 4; ++d) {
+                    T[d] = int(r % uint64_t(g.nb));
+                    r /= uint64_t(g.nb);
+                }
+                ok = T[0] <= T[1] && T[1] <= T[2] && T[2] <= T[3];
+            } else if (map == MAP_REC || map == MAP_REC_LAUNCH) ok = rec4(uint32_t(b), g.lg, g.nb, uint32_t(g.G), T);
+            else { linear4(uint32_t(b), T); ok = true; }
+            for (int d = 0; d < 4; ++d) o[d] = ok ? T[d] : -1;
+        } else if (m == 2) {
             if (map == MAP_LAMBDA) ok = lambda2(uint32_t(b), g.lg, g.nb, X, Y);
             else if (map == MAP_BBOX) { X = int(b % g.nb); Y = int(b / g.nb); ok = X <= Y; }
             else if (map == MAP_BELOW) ok = below2(b, uint32_t(g.nb), X, Y);
@@ -249,18 +289,19 @@ int smx_map_tiles_host(int m, int64_t n, int rho, int map, int64_t first, int64_
 
 static int map_dump(int m, int64_t n, int rho, int map, int strict, int32_t *d_tiles, int64_t *d_stats,
                     void *d_ws, size_t ws_bytes, void *stream) {
-    int rc = check_common(m, n, rho, map, m == 2 ? 1024 : 64);
+    int rc = check_common(m, n, rho, map, max_rho(m));
     if (rc != SMX_OK) return rc;
     if (d_stats != nullptr && (d_ws == nullptr || ws_bytes < kSlotBytes))
         return fail(SMX_EINVAL, "statistics need a workspace of %zu bytes", kSlotBytes);
     if (n == 0) return SMX_OK;
     MapGeom g;
-    if (!make_geom(m, (n + rho - 1) / rho, map, g)) return SMX_EOVERFLOW;
+    if (!make_geom(m, (n + rho - 1) / rho, map, g)) return g_status;
     unsigned long long *slots = d_stats ? reinterpret_cast<unsigned long long *>(d_ws) : nullptr;
     if (slots && (rc = launch_fill_u64(reinterpret_cast<uint64_t *>(slots), kSlotBytes / 8, S(stream))))
         return rc;
-    rc = m == 2 ? launch_map2(g, n, rho, map, strict, d_tiles, slots, S(stream))
-                : launch_map3(g, n, rho, map, strict, d_tiles, slots, S(stream));
+    rc = m == 2   ? launch_map2(g, n, rho, map, strict, d_tiles, slots, S(stream))
+         : m == 3 ? launch_map3(g, n, rho, map, strict, d_tiles, slots, S(stream))
+                  : launch_map4(g, n, rho, strict, d_tiles, slots, S(stream));
     if (rc) return rc;
     if (slots) return launch_stats_finalize(slots, g.G, d_stats, S(stream));
     return SMX_OK;
@@ -276,20 +317,23 @@ int smx_simplex_map3(int64_t n, int rho, int map, int strict, int32_t *d_tiles, 
     return map_dump(3, n, rho, map, strict, d_tiles, d_stats, d_ws, ws_bytes, stream);
 }
 
+int smx_simplex_map4(int64_t n, int rho, int map, int strict, int32_t *d_tiles, int64_t *d_stats,
+                     void *d_ws, size_t ws_bytes, void *stream) {
+    return map_dump(4, n, rho, map, strict, d_tiles, d_stats, d_ws, ws_bytes, stream);
+}
+
 int smx_simplex_count(int m, int64_t n, int rho, int map, int strict, int64_t *d_stats, void *d_ws,
                       size_t ws_bytes, void *stream) {
-    int rc = check_common(m, n, rho, map, m == 2 ? 1024 : 64);
+    int rc = check_common(m, n, rho, map, max_rho(m));
     if (rc != SMX_OK) return rc;
     if (d_stats == nullptr) return fail(SMX_EINVAL, "stats must not be NULL");
     if (d_ws == nullptr || ws_bytes < kSlotBytes)
         return fail(SMX_EINVAL, "a workspace of %zu bytes is required", kSlotBytes);
+    MapGeom g{};
+    if (n > 0 && !make_geom(m, (n + rho - 1) / rho, map, g)) return g_status;
     unsigned long long *slots = reinterpret_cast<unsigned long long *>(d_ws);
     if ((rc = launch_fill_u64(reinterpret_cast<uint64_t *>(slots), kSlotBytes / 8, S(stream)))) return rc;
-    MapGeom g{};
-    if (n > 0) {
-        if (!make_geom(m, (n + rho - 1) / rho, map, g)) return SMX_EOVERFLOW;
-        if ((rc = launch_count(m, g, n, rho, map, strict, slots, S(stream)))) return rc;
-    }
+    if (n > 0 && (rc = launch_count(m, g, n, rho, map, strict, slots, S(stream)))) return rc;
     return launch_stats_finalize(slots, g.G, d_stats, S(stream));
 }
 
@@ -309,7 +353,7 @@ int smx_edm_packed(const float *d_X, int64_t n, int64_t d, int64_t ldx, int map,
         return fail(SMX_EINVAL, "workspace of %zu bytes required (got %zu)", w.total, ws_bytes);
     const int tile = prec == SMX_EDM_FP32_DIFF ? edm_diff_tile(n) : gram_tile(n);
     MapGeom g;
-    if (!make_geom(2, (n + tile - 1) / tile, map, g)) return SMX_EOVERFLOW;
+    if (!make_geom(2, (n + tile - 1) / tile, map, g)) return g_status;
     char *ws = reinterpret_cast<char *>(d_ws);
     unsigned long long *slots = d_stats ? reinterpret_cast<unsigned long long *>(ws + w.slots) : nullptr;
     int rc;
@@ -359,8 +403,8 @@ static int triplet_run(int mode, const float *d_X, int64_t n, int64_t ldx, const
     MapGeom g3, g2;
     const int64_t nb3 = (n + kTripTile - 1) / kTripTile, nb2 = (n + kLjTile - 1) / kLjTile;
     const bool do_at = pot->at_on && n >= 3, do_lj = pot->lj_on && n >= 2;
-    if (do_at && !make_geom(3, nb3, map, g3)) return SMX_EOVERFLOW;
-    if (do_lj && !make_geom(2, nb2, map, g2)) return SMX_EOVERFLOW;
+    if (do_at && !make_geom(3, nb3, map, g3)) return g_status;
+    if (do_lj && !make_geom(2, nb2, map, g2)) return g_status;
 
     char *ws = reinterpret_cast<char *>(d_ws);
     double *eslots = reinterpret_cast<double *>(ws + w.eslots);
@@ -410,14 +454,12 @@ int smx_triplet_packed(const float *d_X, int64_t n, int64_t ldx, double nu, int 
     if (d_stats != nullptr && (d_ws == nullptr || ws_bytes < kSlotBytes))
         return fail(SMX_EINVAL, "statistics need a workspace of %zu bytes", kSlotBytes);
     if (n >= 3 && (d_X == nullptr || d_E == nullptr)) return fail(SMX_EINVAL, "X and E must not be NULL");
+    MapGeom g{};
+    if (n >= 3 && !make_geom(3, (n + kTripTile - 1) / kTripTile, map, g)) return g_status;
     unsigned long long *slots = d_stats ? reinterpret_cast<unsigned long long *>(d_ws) : nullptr;
     int rc;
     if (slots && (rc = launch_fill_u64(reinterpret_cast<uint64_t *>(slots), kSlotBytes / 8, S(stream)))) return rc;
-    MapGeom g{};
-    if (n >= 3) {
-        if (!make_geom(3, (n + kTripTile - 1) / kTripTile, map, g)) return SMX_EOVERFLOW;
-        if ((rc = launch_triplet_packed(g, d_X, n, ldx, float(nu), d_E, slots, S(stream)))) return rc;
-    }
+    if (n >= 3 && (rc = launch_triplet_packed(g, d_X, n, ldx, float(nu), d_E, slots, S(stream)))) return rc;
     if (slots) return launch_stats_finalize(slots, g.G, d_stats, S(stream));
     return SMX_OK;
 }

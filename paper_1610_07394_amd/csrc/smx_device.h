@@ -81,6 +81,39 @@ __device__ __forceinline__ bool tile3_of(const MapGeom &g, uint64_t &lin, int &X
     return true;
 }
 
+// 4-simplex tiles (X[0] <= X[1] <= X[2] <= X[3]).  There is no 4-D hardware
+// grid: every map, the bounding box included, runs on a 1-D (or 2-D) launch,
+// and the bounding box decodes its block index with divisions by nb.  The
+// from-below map is not defined for m = 4 (the host rejects it).
+template <int MAP, bool XCD>
+__device__ __forceinline__ bool tile4_of(const MapGeom &g, uint64_t &lin, int X[4]) {
+    lin = uint64_t(blockIdx.y) * gridDim.x + blockIdx.x;
+    if (lin >= g.G) return false;
+    const uint32_t id = XCD ? xcd_remap(uint32_t(lin), uint32_t(g.G)) : uint32_t(lin);
+    lin = id;
+    if (MAP == MAP_BBOX) {
+        const uint32_t nb = uint32_t(g.nb);
+        uint32_t r = id;
+        for (int d = 0; d < 4; ++d) {
+            const uint32_t q = r / nb;
+            X[d] = int(r - q * nb);
+            r = q;
+        }
+        return X[0] <= X[1] && X[1] <= X[2] && X[2] <= X[3];
+    }
+    if (MAP == MAP_LAMBDA) return lambda4(id, g.lg, g.nb, g.main, X);
+    if (MAP == MAP_REC) return rec4(id, g.lg, g.nb, uint32_t(g.G), X);
+    if (MAP == MAP_CUBE) {
+        lin = g.off + id;
+        return cube4(id, g, X);
+    }
+    if (MAP == MAP_LINEAR) {
+        linear4(id, X);
+        return true;
+    }
+    return false;
+}
+
 // SplitMix64 finaliser (Steele, Lea, Flood, OOPSLA 2014): the output function
 // applied to state x + golden-ratio increment.
 __device__ __forceinline__ uint64_t mix64(uint64_t x) {
@@ -100,6 +133,12 @@ __device__ __forceinline__ uint64_t id_trip_le(uint64_t i, uint64_t j, uint64_t 
 }
 __device__ __forceinline__ uint64_t id_trip_lt(uint64_t i, uint64_t j, uint64_t k) {
     return (k * (k - 1) * (k - 2)) / 6 + (j * (j - 1)) / 2 + i;
+}
+__device__ __forceinline__ uint64_t id_quad_le(uint64_t i, uint64_t j, uint64_t k, uint64_t l) {
+    return (l * (l + 1) * (l + 2) * (l + 3)) / 24 + (k * (k + 1) * (k + 2)) / 6 + (j * (j + 1)) / 2 + i;
+}
+__device__ __forceinline__ uint64_t id_quad_lt(uint64_t i, uint64_t j, uint64_t k, uint64_t l) {
+    return (l * (l - 1) * (l - 2) * (l - 3)) / 24 + (k * (k - 1) * (k - 2)) / 6 + (j * (j - 1)) / 2 + i;
 }
 
 template <typename T>

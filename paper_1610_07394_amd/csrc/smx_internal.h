@@ -18,7 +18,7 @@ int check_launch(const char *what);
 // Kernel ids for the timing facility (match smx_profile_read).
 enum KernelId {
     K_MAP2 = 0, K_MAP3 = 1, K_EDM_DIFF = 2, K_EDM_GRAM = 3, K_GRAM_PREP = 4,
-    K_TRIP_ENERGY = 5, K_TRIP_GRAD = 6, K_LJ = 7, K_FINALIZE = 8, K_TRIP_PACKED = 9, K_COUNT = 10
+    K_TRIP_ENERGY = 5, K_TRIP_GRAD = 6, K_LJ = 7, K_FINALIZE = 8, K_TRIP_PACKED = 9, K_MAP4 = 10, K_COUNT = 11
 };
 void prof_begin(int kid, hipStream_t s);
 void prof_end(int kid, hipStream_t s);
@@ -52,20 +52,22 @@ inline void map_switch(int map, F &&f) {
 // side 2^(lg-1) at p + 2^(lg-1) e_d; a side-1 simplex is one block.  c.off
 // advances by the blocks of each launch.
 template <typename F>
-inline void rec_launches(MapGeom &c, int lg, int32_t p0, int32_t p1, int32_t p2, F &f) {
+inline void rec_launches(MapGeom &c, int lg, int32_t p0, int32_t p1, int32_t p2, int32_t p3, F &f) {
     const int h = lg > 0 ? lg - 1 : 0;
     c.c0 = p0;
     c.c1 = p1;
     c.c2 = p2;
+    c.c3 = p3;
     c.lg = h;
     c.G = uint64_t(1) << (c.dim * h);
     f(std::integral_constant<int, MAP_CUBE>{}, static_cast<const MapGeom &>(c));
     c.off += c.G;
     if (lg == 0) return;
     const int32_t s = int32_t(1) << h;
-    rec_launches(c, h, p0 + s, p1, p2, f);
-    rec_launches(c, h, p0, p1 + s, p2, f);
-    if (c.dim == 3) rec_launches(c, h, p0, p1, p2 + s, f);
+    rec_launches(c, h, p0 + s, p1, p2, p3, f);
+    rec_launches(c, h, p0, p1 + s, p2, p3, f);
+    if (c.dim >= 3) rec_launches(c, h, p0, p1, p2 + s, p3, f);
+    if (c.dim >= 4) rec_launches(c, h, p0, p1, p2, p3 + s, f);
 }
 
 // Call f(std::integral_constant<int, MAP>{}, geom) for every launch that the
@@ -77,7 +79,7 @@ inline void for_each_launch(const MapGeom &g, F &&f) {
         MapGeom c = g;
         c.map = MAP_CUBE;
         c.off = 0;
-        rec_launches(c, g.lg, 0, 0, 0, f);
+        rec_launches(c, g.lg, 0, 0, 0, 0, f);
         return;
     }
     map_switch(int(g.map), [&](auto M) { f(M, g); });
@@ -96,6 +98,8 @@ int launch_stats_finalize(const unsigned long long *slots, uint64_t launched, in
 int launch_map2(const MapGeom &g, int64_t n, int rho, int map, int strict, int32_t *tiles,
                 unsigned long long *slots, hipStream_t s);
 int launch_map3(const MapGeom &g, int64_t n, int rho, int map, int strict, int32_t *tiles,
+                unsigned long long *slots, hipStream_t s);
+int launch_map4(const MapGeom &g, int64_t n, int rho, int strict, int32_t *tiles,
                 unsigned long long *slots, hipStream_t s);
 int launch_count(int m, const MapGeom &g, int64_t n, int rho, int map, int strict,
                  unsigned long long *slots, hipStream_t s);

@@ -109,6 +109,36 @@ __global__ __launch_bounds__(kMapThreads) void map3_kernel(MapGeom g, int64_t n,
     if (threadIdx.x == 0) stats_add(slots, lin, c, h);
 }
 
+template <int MAP, bool STRICT>
+__global__ __launch_bounds__(kMapThreads) void map4_kernel(MapGeom g, int64_t n, int rho, int lgrho,
+                                                          int32_t *tiles, unsigned long long *slots) {
+    uint64_t lin;
+    int X[4] = {-1, -1, -1, -1};
+    const bool ok = tile4_of<MAP, false>(g, lin, X);
+    if (launch_tail<MAP_LINEAR>(g)) return;  // every m = 4 map runs on a 1-D / 2-D launch
+    if (tiles != nullptr && threadIdx.x == 0) {
+        for (int d = 0; d < 4; ++d) tiles[4 * lin + d] = ok ? X[d] : -1;
+    }
+    if (!ok || slots == nullptr) return;
+    __shared__ unsigned long long red[2][kMapThreads / kWave];
+    unsigned long long cnt = 0, cs = 0;
+    const int64_t i0 = int64_t(X[0]) * rho, j0 = int64_t(X[1]) * rho, k0 = int64_t(X[2]) * rho,
+                  l0 = int64_t(X[3]) * rho;
+    const int rmask = rho - 1;
+    for (int e = threadIdx.x; e < rho * rho * rho * rho; e += kMapThreads) {
+        const int64_t i = i0 + (e >> (3 * lgrho)), j = j0 + ((e >> (2 * lgrho)) & rmask),
+                      k = k0 + ((e >> lgrho) & rmask), l = l0 + (e & rmask);
+        const bool v = l < n && (STRICT ? (i < j && j < k && k < l) : (i <= j && j <= k && k <= l));
+        if (v) {
+            ++cnt;
+            cs += mix64(STRICT ? id_quad_lt(i, j, k, l) : id_quad_le(i, j, k, l));
+        }
+    }
+    const unsigned long long c = block_sum<unsigned long long, kMapThreads>(cnt, red[0]);
+    const unsigned long long h = block_sum<unsigned long long, kMapThreads>(cs, red[1]);
+    if (threadIdx.x == 0) stats_add(slots, lin, c, h);
+}
+
 // Element count of one tile in closed form: t = elements of a tile edge that
 // lie below n; a diagonal pair of tile coordinates holds a triangle, a
 // diagonal triple a tetrahedron.
@@ -163,13 +193,48 @@ __global__ __launch_bounds__(kMapThreads) void count3_kernel(MapGeom g, int64_t 
     atomicAdd(s + 2, 1ull);
 }
 
+// Elements of a 4-simplex tile: consecutive equal tile coordinates form runs;
+// a run of r equal coordinates with edge length t holds C(t + r - 1, r) (or
+// C(t, r) strict) sorted r-tuples, and distinct runs multiply.
+__device__ __forceinline__ uint64_t run_cnt(uint64_t t, int r, bool strict) {
+    uint64_t v = 1;
+    for (int q = 0; q < r; ++q) v = v * (strict ? t - uint64_t(q) : t + uint64_t(q)) / uint64_t(q + 1);
+    return strict && t < uint64_t(r) ? 0 : v;
+}
+
+template <int MAP, bool STRICT>
+__global__ __launch_bounds__(kMapThreads) void count4_kernel(MapGeom g, int64_t n, int rho,
+                                                            unsigned long long *slots) {
+    if (threadIdx.x >= kWave) return;
+    uint64_t lin;
+    int X[4];
+    if (!tile4_of<MAP, false>(g, lin, X)) return;
+    if (threadIdx.x != 0) return;
+    uint64_t cnt = 1;
+    int d = 0;
+    while (d < 4) {
+        int r = 1;
+        while (d + r < 4 && X[d + r] == X[d]) ++r;
+        cnt *= run_cnt(edge_len(X[d], rho, n), r, STRICT);
+        d += r;
+    }
+    unsigned long long *s = slots + (lin % kSlots) * kSlotStride;
+    atomicAdd(s + 0, (unsigned long long)cnt);
+    atomicAdd(s + 2, 1ull);
+}
+
 int launch_count(int m, const MapGeom &g, int64_t n, int rho, int map, int strict,
                  unsigned long long *slots, hipStream_t s) {
-    prof_begin(m == 2 ? K_MAP2 : K_MAP3, s);
+    const int kid = m == 2 ? K_MAP2 : m == 3 ? K_MAP3 : K_MAP4;
+    prof_begin(kid, s);
     (void)map;
     for_each_launch(g, [&](auto M, const MapGeom &g) {
         constexpr int MAPK = decltype(M)::value;
-        if (m == 2) {
+        if (m == 4) {
+            const dim3 grid = grid_for(g.G, kMapThreads);
+            if (strict) hipLaunchKernelGGL((count4_kernel<MAPK, true>), grid, dim3(kMapThreads), 0, s, g, n, rho, slots);
+            else hipLaunchKernelGGL((count4_kernel<MAPK, false>), grid, dim3(kMapThreads), 0, s, g, n, rho, slots);
+        } else if (m == 2) {
             const dim3 grid = MAPK == MAP_BBOX ? dim3(g.nb, g.nb, 1) : grid_for(g.G, kMapThreads);
             if (strict) hipLaunchKernelGGL((count2_kernel<MAPK, true>), grid, dim3(kMapThreads), 0, s, g, n, rho, slots);
             else hipLaunchKernelGGL((count2_kernel<MAPK, false>), grid, dim3(kMapThreads), 0, s, g, n, rho, slots);
@@ -179,7 +244,7 @@ int launch_count(int m, const MapGeom &g, int64_t n, int rho, int map, int stric
             else hipLaunchKernelGGL((count3_kernel<MAPK, false>), grid, dim3(kMapThreads), 0, s, g, n, rho, slots);
         }
     });
-    prof_end(m == 2 ? K_MAP2 : K_MAP3, s);
+    prof_end(kid, s);
     return check_launch("simplex_count");
 }
 
@@ -205,6 +270,27 @@ static void go_map3(const MapGeom &g, int64_t n, int rho, int lgrho, int strict,
     else
         hipLaunchKernelGGL((map3_kernel<MAP, false>), grid, dim3(kMapThreads), 0, s, g, n, rho, lgrho,
                            tiles, slots);
+}
+
+template <int MAP>
+static void go_map4(const MapGeom &g, int64_t n, int rho, int lgrho, int strict, int32_t *tiles,
+                    unsigned long long *slots, hipStream_t s) {
+    const dim3 grid = grid_for(g.G, kMapThreads);
+    if (strict)
+        hipLaunchKernelGGL((map4_kernel<MAP, true>), grid, dim3(kMapThreads), 0, s, g, n, rho, lgrho,
+                           tiles, slots);
+    else
+        hipLaunchKernelGGL((map4_kernel<MAP, false>), grid, dim3(kMapThreads), 0, s, g, n, rho, lgrho,
+                           tiles, slots);
+}
+
+int launch_map4(const MapGeom &g, int64_t n, int rho, int strict, int32_t *tiles,
+                unsigned long long *slots, hipStream_t s) {
+    const int lgrho = floor_log2_u32(uint32_t(rho));
+    prof_begin(K_MAP4, s);
+    for_each_launch(g, [&](auto M, const MapGeom &gg) { go_map4<decltype(M)::value>(gg, n, rho, lgrho, strict, tiles, slots, s); });
+    prof_end(K_MAP4, s);
+    return check_launch("simplex_map4");
 }
 
 int launch_map2(const MapGeom &g, int64_t n, int rho, int map, int strict, int32_t *tiles,

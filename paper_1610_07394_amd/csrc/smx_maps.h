@@ -5,7 +5,8 @@
 // s_lshl / s_lshr for powers of two) and costs no vector ALU slots.  The same
 // inline code is compiled for the host so the host-side query can evaluate it.
 //
-// Tile targets: T2 = {X <= Y < nb}, T3 = {X <= Y <= Z < nb}.
+// Tile targets: T2 = {X <= Y < nb}, T3 = {X <= Y <= Z < nb},
+// T4 = {X1 <= X2 <= X3 <= X4 < nb}.
 #pragma once
 #include <stdint.h>
 
@@ -41,7 +42,7 @@ struct MapGeom {
     uint32_t map;   // MapKind of the launch
     uint64_t G;     // logical blocks launched
     int32_t dim;    // m, the simplex dimension
-    int32_t c0, c1, c2;  // MAP_CUBE: corner-coordinate origin of the sub-orthotope
+    int32_t c0, c1, c2, c3;  // MAP_CUBE: corner-coordinate origin of the sub-orthotope
     uint64_t off;   // MAP_CUBE: position of its first block in the whole set
 };
 
@@ -195,6 +196,31 @@ SMX_HD void linear3(uint32_t k, int &X, int &Y, int &Z) {
     Z = int(z);
     Y = int(y);
     X = int(r - tri_u64(y));
+}
+
+// 4-simplex: block k is the k-th tile of T4 listed by X4, X3, X2, X1.
+SMX_HD uint64_t pen_u64(uint64_t w) { return w * (w + 1) * (w + 2) * (w + 3) / 24; }
+
+SMX_HD uint32_t pen_root(uint64_t k) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    const float f = __builtin_sqrtf(__builtin_sqrtf(24.0f * float(k)));
+#else
+    const float f = std::sqrt(std::sqrt(24.0f * float(k)));
+#endif
+    uint64_t w = f > 2.0f ? uint64_t(f) - 2 : 0;
+    while (w > 0 && pen_u64(w) > k) --w;
+    while (pen_u64(w + 1) <= k) ++w;
+    return uint32_t(w);
+}
+
+SMX_HD void linear4(uint32_t k, int X[4]) {
+    const uint32_t w = pen_root(k);
+    int t[3];
+    linear3(uint32_t(uint64_t(k) - pen_u64(w)), t[0], t[1], t[2]);
+    X[0] = t[0];
+    X[1] = t[1];
+    X[2] = t[2];
+    X[3] = int(w);
 }
 
 // ---------------------------------------------------------------- from below
@@ -372,6 +398,42 @@ SMX_HD bool rec3(uint32_t id, int lg, int nb, uint32_t V, int &X, int &Y, int &Z
     return a + b + c < uint32_t(nb);
 }
 
+SMX_HD bool rec4(uint32_t id, int lg, int nb, uint32_t V, int X[4]) {
+    uint32_t p0 = 0, p1 = 0, p2 = 0, p3 = 0;
+    for (int l = lg; l > 0; --l) {
+        const int h = l - 1;
+        const uint32_t cube = 1u << (4 * h);
+        if (id < cube) {
+            const uint32_t mask = (1u << h) - 1u;
+            p0 += id & mask;
+            p1 += (id >> h) & mask;
+            p2 += (id >> (2 * h)) & mask;
+            p3 += id >> (3 * h);
+            break;
+        }
+        id -= cube;
+        const uint32_t vh = (V - cube) >> 2;
+        if (id < vh) {
+            p0 += 1u << h;
+        } else if (id < 2 * vh) {
+            p1 += 1u << h;
+            id -= vh;
+        } else if (id < 3 * vh) {
+            p2 += 1u << h;
+            id -= 2 * vh;
+        } else {
+            p3 += 1u << h;
+            id -= 3 * vh;
+        }
+        V = vh;
+    }
+    X[0] = int(p0);
+    X[1] = int(p0 + p1);
+    X[2] = int(p0 + p1 + p2);
+    X[3] = int(p0 + p1 + p2 + p3);
+    return p0 + p1 + p2 + p3 < uint32_t(nb);
+}
+
 // One sub-orthotope of the recursive set on its own launch (MAP_CUBE): block
 // id of the cube of side 2^g.lg at corner origin (c0, c1[, c2]), x fastest.
 SMX_HD bool cube2(uint32_t id, const MapGeom &g, int &X, int &Y) {
@@ -391,6 +453,101 @@ SMX_HD bool cube3(uint32_t id, const MapGeom &g, int &X, int &Y, int &Z) {
     Y = int(a + b);
     Z = int(a + b + c);
     return a + b + c < uint32_t(g.nb);
+}
+
+SMX_HD bool cube4(uint32_t id, const MapGeom &g, int X[4]) {
+    const uint32_t mask = (1u << g.lg) - 1u;
+    const uint32_t a = uint32_t(g.c0) + (id & mask);
+    const uint32_t b = uint32_t(g.c1) + ((id >> g.lg) & mask);
+    const uint32_t c = uint32_t(g.c2) + ((id >> (2 * g.lg)) & mask);
+    const uint32_t d = uint32_t(g.c3) + (id >> (3 * g.lg));
+    X[0] = int(a);
+    X[1] = int(a + b);
+    X[2] = int(a + b + c);
+    X[3] = int(a + b + c + d);
+    return a + b + c + d < uint32_t(g.nb);
+}
+
+// ---------------------------------------------------------------- lambda4
+// The 4-simplex map built on the r = 1/2, beta = 2 recursive set of Sec. III-D
+// (the paper gives that set and its volume (n^4 - n)/14, not a map).  T4 is
+// split into T4s = {X1 <= X2 <= X3 < X4} and the plane X3 = X4 (a copy of T3).
+// A tuple of T4s belongs to the node of the binary recursion on [0, nb') --
+// offset o, size 2b -- where X1 and X4 first fall on different halves
+// L = [o, o+b), H = [o+b, o+2b); its cross region is
+//   R3 = {X1 <= X2 <= X3 in L, X4 in H}     b C(b+2, 3) tiles
+//   R2 = {X1 <= X2 in L, X3 < X4 in H}      C(b+1, 2) C(b, 2)
+//   R1 = {X1 in L, X2 <= X3 < X4 in H}      b C(b+1, 3)
+// b^2 (b+1)(7b-1)/12 <= b^4 tiles.  Each node owns one b^4 orthotope of blocks:
+// level l (b = nb'/2^(l+1)) holds 2^l nodes, 2^(4 lg - 3l - 4) blocks, and the
+// levels add up to (nb'^4 - nb')/14.  Within a node the leading blocks unrank
+// R3, R2, R1 in turn (the sorted triples and pairs by the exact-root linear
+// maps above, the free coordinate fastest); the rest are filtered (the 5/7
+// extra volume of the set).  Blocks past the orthotopes form a lambda3 grid over
+// nb whose tile (X, Y, Z) becomes (X, Y, Z, Z).  The level is found in at most
+// lg block-uniform steps.
+SMX_HD uint64_t lambda4_main_blocks(int lg) {
+    uint64_t v = 0;
+    for (int l = 0; l < lg; ++l) v += uint64_t(1) << (4 * lg - 3 * l - 4);
+    return v;
+}
+
+SMX_HD bool lambda4(uint32_t id, int lg, int nb, uint32_t main, int X[4]) {
+    if (id >= main) {
+        int x, y, z;
+        if (!lambda3(id - main, lg, nb, lambda3_main_blocks(lg), x, y, z)) return false;
+        X[0] = x;
+        X[1] = y;
+        X[2] = z;
+        X[3] = z;
+        return true;
+    }
+    int l = 0;
+    uint32_t r = id;
+    for (;;) {
+        const uint32_t sz = 1u << (4 * lg - 3 * l - 4);
+        if (r < sz) break;
+        r -= sz;
+        ++l;
+    }
+    const int h = lg - l - 1;
+    const uint32_t b = 1u << h;
+    const uint32_t o = (r >> (4 * h)) << (h + 1);
+    uint32_t loc = r & ((1u << (4 * h)) - 1u);
+    int t[3];
+    const uint32_t n3 = b * (b * (b + 1) * (b + 2) / 6);
+    if (loc < n3) {
+        linear3(loc >> h, t[0], t[1], t[2]);
+        X[0] = int(o) + t[0];
+        X[1] = int(o) + t[1];
+        X[2] = int(o) + t[2];
+        X[3] = int(o + b + (loc & (b - 1u)));
+        return X[3] < nb;
+    }
+    loc -= n3;
+    const uint32_t P = b * (b + 1) / 2, Q = b * (b - 1) / 2;
+    if (loc < P * Q) {
+        const uint32_t p = loc / Q, s = loc - p * Q;
+        int a, c;
+        linear2(p, a, c);
+        const uint32_t y = tri_root(s);  // strict pair (d < e): e = y + 1, d = s - y(y+1)/2
+        X[0] = int(o) + a;
+        X[1] = int(o) + c;
+        X[2] = int(o + b + (s - y * (y + 1) / 2));
+        X[3] = int(o + b + y + 1);
+        return X[3] < nb;
+    }
+    loc -= P * Q;
+    const uint32_t n1 = b * ((b + 1) * b * (b - 1) / 6);
+    if (loc < n1) {
+        linear3(loc >> h, t[0], t[1], t[2]);  // X2 <= X3 <= X4 - 1 in H
+        X[0] = int(o + (loc & (b - 1u)));
+        X[1] = int(o + b) + t[0];
+        X[2] = int(o + b) + t[1];
+        X[3] = int(o + b) + t[2] + 1;
+        return X[3] < nb;
+    }
+    return false;
 }
 
 // ---------------------------------------------------------------- XCD order

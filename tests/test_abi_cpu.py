@@ -36,7 +36,7 @@ def test_version_and_volume():
         assert smx.volume(2, n, strict=True) == n * (n - 1) // 2 if n > 0 else smx.volume(2, n, True) == 0
         assert smx.volume(3, n) == n * (n + 1) * (n + 2) // 6
         assert smx.volume(3, n, strict=True) == max(0, n * (n - 1) * (n - 2) // 6)
-    assert smx.volume(4, 10) == -1
+    assert smx.volume(5, 10) == -1
     assert smx.volume(2, -1) == -1
 
 
@@ -70,6 +70,33 @@ def test_host_map3_equals_oracle(nb, kind):
     got = smx.map_tiles_host(3, nb, 1, kind)
     want = omaps.tiles(3, nb, kind)
     np.testing.assert_array_equal(got, want)
+
+
+@pytest.mark.parametrize("nb", [1, 2, 3, 4, 5, 8, 9, 16, 17, 32, 33, 64])
+@pytest.mark.parametrize("kind", ["lambda", "bbox", "linear", "recursive", "recursive_launch"])
+def test_host_map4_equals_oracle(nb, kind):
+    if kind == "bbox" and nb > 33:
+        pytest.skip("bbox dump of nb^4 blocks checked at smaller nb")
+    got = smx.map_tiles_host(4, nb, 1, kind)
+    want = omaps.tiles(4, nb, kind)
+    np.testing.assert_array_equal(got, want)
+
+
+def test_map4_limits_and_volume():
+    from math import comb
+    for n in (0, 1, 3, 4, 10, 1000):
+        assert smx.volume(4, n) == comb(n + 3, 4) and smx.volume(4, n, True) == comb(n, 4)
+    assert smx.parallel_blocks(4, 2048, 16, "lambda") == omaps.lambda4_blocks(128)
+    assert smx.parallel_blocks(4, 2048, 16, "linear") == comb(131, 4)
+    L = smx.lib()
+    null = None
+    # from below is not defined for m = 4; rho past 16; m = 5
+    assert L.smx_simplex_count(4, 100, 1, 3, 0, ctypes.c_void_p(256), ctypes.c_void_p(256), 1 << 20, null) == 3
+    assert L.smx_simplex_map4(100, 32, 0, 0, null, null, null, 0, null) == 1
+    assert L.smx_simplex_count(5, 100, 1, 0, 0, ctypes.c_void_p(256), ctypes.c_void_p(256), 1 << 20, null) == 1
+    # bounding box past 2^31 blocks; lambda4 past nb' = 256
+    assert L.smx_parallel_blocks(4, 256 * 16, 16, 1) == -1
+    assert L.smx_parallel_blocks(4, 257 * 16, 16, 0) == -1
 
 
 def test_linear_map_exact_where_fp32_roots_are_not():
@@ -107,7 +134,7 @@ def test_validation_errors_before_any_device_work():
     # n = 0 is a no-op
     assert L.smx_simplex_map2(0, 16, 0, 0, null, null, null, 0, null) == 0
     # parallel-space count: bad m / rho / map, no stats, no workspace
-    assert L.smx_simplex_count(4, 16, 1, 0, 0, ctypes.c_void_p(256), ctypes.c_void_p(256), 1 << 20, null) == 1
+    assert L.smx_simplex_count(5, 16, 1, 0, 0, ctypes.c_void_p(256), ctypes.c_void_p(256), 1 << 20, null) == 1
     assert L.smx_simplex_count(2, 16, 3, 0, 0, ctypes.c_void_p(256), ctypes.c_void_p(256), 1 << 20, null) == 1
     assert L.smx_simplex_count(2, 16, 1, 9, 0, ctypes.c_void_p(256), ctypes.c_void_p(256), 1 << 20, null) == 1
     assert L.smx_simplex_count(2, 16, 1, 0, 0, null, ctypes.c_void_p(256), 1 << 20, null) == 1

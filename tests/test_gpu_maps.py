@@ -2,6 +2,7 @@
 maps, element counts and checksums exact against the oracle's simplex
 checksums, for the lambda, bounding-box and linear maps."""
 import json
+import math
 import os
 
 import numpy as np
@@ -40,7 +41,7 @@ def _check_stats(s, m, n, rho, kind, strict):
     V = oracle.simplex_volume(m, n, strict)
     assert int(s[0]) == V
     assert _u64(s[1]) == oracle.checksum_range(V)
-    ntiles = nb * (nb + 1) // 2 if m == 2 else nb * (nb + 1) * (nb + 2) // 6
+    ntiles = math.comb(nb + m - 1, m)
     assert int(s[2]) == ntiles
     assert int(s[3]) == smx.parallel_blocks(m, n, rho, kind)
 
@@ -70,6 +71,38 @@ def test_map3_dump_and_counts(n, rho, kind, strict):
     nb = -(-n // rho)
     np.testing.assert_array_equal(t, omaps.tiles(3, nb, kind))
     _check_stats(s, 3, n, rho, kind, strict)
+
+
+KINDS4 = ["lambda", "bbox", "linear", "recursive", "recursive_launch"]
+CASES4 = [(16, 1), (17, 1), (1, 4), (30, 2), (64, 4), (100, 8), (130, 16), (256, 16)]
+
+
+@pytest.mark.parametrize("n,rho", CASES4)
+@pytest.mark.parametrize("kind", KINDS4)
+@pytest.mark.parametrize("strict", [False, True])
+def test_map4_dump_and_counts(n, rho, kind, strict):
+    print(f"map4 n={n} rho={rho} {kind} strict={strict}", flush=True)
+    t, s = smx.simplex_map4(n, rho, kind, strict=strict)
+    torch.cuda.synchronize()
+    nb = -(-n // rho)
+    np.testing.assert_array_equal(t.cpu().numpy(), omaps.tiles(4, nb, kind))
+    _check_stats(s.cpu().numpy(), 4, n, rho, kind, strict)
+
+
+@pytest.mark.parametrize("n,rho", [(2048, 16), (1000, 8), (33 * 16, 16), (7, 1)])
+@pytest.mark.parametrize("kind", KINDS4)
+@pytest.mark.parametrize("strict", [False, True])
+def test_count4_closed_form(n, rho, kind, strict):
+    """4-simplex parallel space at n = 2048, rho = 16 (nb = 128: 1.9e7 lambda4
+    blocks, 2.7e8 bounding-box blocks): the closed-form tile counts add up to
+    the volume."""
+    if kind == "bbox" and -(-n // rho) > 215:
+        pytest.skip("nb^4 blocks exceed the launch limit")
+    s = smx.simplex_count(4, n, rho, kind, strict).cpu().numpy()
+    nb = -(-n // rho)
+    assert int(s[0]) == oracle.simplex_volume(4, n, strict)
+    assert int(s[2]) == nb * (nb + 1) * (nb + 2) * (nb + 3) // 24
+    assert int(s[3]) == smx.parallel_blocks(4, n, rho, kind)
 
 
 @pytest.mark.parametrize("kind", KINDS)
