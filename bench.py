@@ -45,6 +45,7 @@ N_EDM, D_EDM = 65536, 64
 N_GRAM, D_GRAM = 32768, 512
 N_AT = 8192
 N_MAP4 = 1024  # 4-simplex map-only comparison: 8^4-element tiles, nb = 128
+QUAD_RC = 2.0  # contact radius of the 4-point contact count (mean contact degree ~34)
 
 
 def parse():
@@ -235,6 +236,33 @@ def main():
             "write_ceiling_fill_gbs": 4 * mpk / t_fill / 1e9,
             "per_unit": "4 bytes written per triplet (i < j < k), 1.430e9 triplets per launch"}
         del Ep, Xp
+
+    # 4-point contacts over the 4-simplex, n = 8192 (measured beside the step):
+    # contact words over the 2-simplex, then the 4-cliques per 64^4 tile
+    if "at" in only and not args.no_compare:
+        qd = {}
+        ws4 = torch.empty(smx.workspace_bytes(3, N_AT), dtype=torch.uint8, device=dev)
+        cnt = torch.empty(1, dtype=torch.int64, device=dev)
+        for kind in ("lambda", "bbox", "linear", "recursive", "recursive_launch"):
+            smx.quad_contacts(X5, QUAD_RC, kind, out=cnt, ws=ws4)
+            torch.cuda.synchronize()
+            smx.profile_enable(True)
+            smx.profile_reset()
+            for _ in range(args.steps):
+                smx.quad_contacts(X5, QUAD_RC, kind, out=cnt, ws=ws4)
+            w_ms, w_c = smx.profile_read("quad_words")
+            q_ms, q_c = smx.profile_read("quad")
+            smx.profile_enable(False)
+            qd[kind] = {"words_ms": w_ms / w_c, "quad_ms": q_ms / q_c,
+                        "blocks": smx.parallel_blocks(4, N_AT, 64, kind)}
+        nq = math.comb(N_AT, 4)
+        t = (qd["lambda"]["words_ms"] + qd["lambda"]["quad_ms"]) / 1e3
+        comps["quad_contacts_n8192"] = {
+            "quadruplets": nq, "contact_radius": QUAD_RC, "cliques": int(cnt.item()),
+            "ms": t * 1e3, "quadruplets_per_s": nq / t, "maps": qd,
+            "speedup_lambda_vs_bbox": (qd["bbox"]["words_ms"] + qd["bbox"]["quad_ms"]) / (t * 1e3),
+            "per_unit": "64^4 quadruplets per block; 3 KB of contact words read per block"}
+        del ws4
 
     # dominant kernel (largest time per step)
     per_step = {k: kern[k][0] / args.steps for k in kern}

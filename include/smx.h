@@ -137,8 +137,8 @@ int smx_map_tiles_host(int m, int64_t n, int rho, int map, int64_t first, int64_
                        int32_t *tiles);
 
 /* Workspace bytes the calls below need (0 if none).  `op`: 0 = simplex_map
- * (any m), 1 = edm_packed, 2 = triplet calls.  Host only; 0 also on bad
- * arguments. */
+ * (any m), 1 = edm_packed, 2 = triplet calls, 3 = quad_contacts.  Host only;
+ * 0 also on bad arguments. */
 size_t smx_workspace_bytes(int op, int64_t n, int64_t d, int prec, int map);
 
 /* Map dump over the 2-simplex (Sec. III-A).  Launches the parallel space of
@@ -261,6 +261,31 @@ int smx_triplet_energy_backward(const float *d_X, int64_t n, int64_t ldx, const 
 int smx_triplet_packed(const float *d_X, int64_t n, int64_t ldx, double nu, int map, float *d_E, void *d_ws,
                        size_t ws_bytes, int64_t *d_stats, void *stream);
 
+/* 4-point contacts on the 4-simplex (Sec. I: correlation counts over the
+ * simplex; Sec. III-D: the 4-simplex parallel space).  Counts the quadruplets
+ * i < j < k < l whose six pairs are all in contact -- the 4-cliques of the
+ * contact graph -- where a pair i < j is in contact when the FP32 squared
+ * distance fl(fma(dz,dz, fma(dy,dy, dx*dx))), d* = fl(x_j* - x_i*), is below
+ * fl(rc*rc).  Two passes over 64-element tiles: contact bit words over the
+ * 2-simplex (map `map` with m = 2), then the cliques over the 4-simplex (map
+ * `map` with m = 4; LAMBDA is the lambda4 map of smx_simplex_map4).
+ *   d_X      FP32 [n][ldx] device, x, y, z in columns 0..2; ldx >= 3.
+ *   n        0 <= n <= 16384 (n < 4 gives 0).
+ *   rc       contact radius, finite and >= 0.
+ *   map      smx_map; LAMBDA_BELOW is not defined for m = 4 (SMX_EUNSUPPORTED).
+ *   d_count  int64[1] device: the number of 4-cliques (exact).
+ *   d_ws     smx_workspace_bytes(3, n, 3, 0, map) bytes of device memory:
+ *            count and statistics slots, then the contact words, 64-bit,
+ *            column-tile-major: word [Y][64 X + p] holds the contacts of row
+ *            64 X + p with columns 64 Y .. 64 Y + 63 (upper tiles X <= Y only).
+ *   d_stats  int64[4] or NULL: [0] quadruplets covered (C(n, 4) when every tile
+ *            is visited once), [1] 0, [2] mapped 4-simplex blocks, [3] 4-simplex
+ *            blocks launched.
+ * Asynchronous on `stream`; the result is exact, so every map returns the same
+ * count. */
+int smx_quad_contacts(const float *d_X, int64_t n, int64_t ldx, double rc, int map, int64_t *d_count,
+                      void *d_ws, size_t ws_bytes, int64_t *d_stats, void *stream);
+
 /* d_out[q] = gradE[0] * d_G[q] for q < 3n (FP32 out, FP64 scale): the backward
  * pass of smx_triplet_energy_grad's output, given the incoming gradient
  * d_gradE (FP64 device scalar).  d_out may alias d_G. */
@@ -270,7 +295,8 @@ int smx_scale_grad(const float *d_G, int64_t n, const double *d_gradE, float *d_
  * events on its own stream.  smx_profile_read synchronises on those events and
  * returns the summed duration (ms) and launch count of kernel `kernel_id`
  * (0 map2, 1 map3, 2 edm diff, 3 edm gram, 4 gram prep, 5 triplet energy,
- * 6 triplet grad, 7 lj, 8 finalize, 9 triplet packed, 10 map4) since the last reset; it
+ * 6 triplet grad, 7 lj, 8 finalize, 9 triplet packed, 10 map4, 11 contact words,
+ * 12 quad contacts) since the last reset; it
  * returns SMX_EINVAL
  * for an unknown id.  smx_profile_reset clears the totals.  Host only. */
 int smx_profile_enable(int on);

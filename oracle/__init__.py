@@ -5,14 +5,19 @@ library computes, written from the paper (Navarro, Bustos, Hitschfeld,
 "Possibilities of Recursive GPU Mapping for Discrete Orthogonal Simplices"):
 
 * ``maps``          -- the block-space maps (lambda2 of Sec. III-A, the lambda3
-                       reading of Sec. III-C, bounding box and linear
-                       enumeration of Sec. I), integer arithmetic only.
+                       reading of Sec. III-C, from below, the recursive sets of
+                       Sec. III-B, the 4-simplex map on the set of Sec. III-D,
+                       bounding box and linear enumeration of Sec. I), integer
+                       arithmetic only.
 * ``edm_rows`` / ``edm_packed`` / ``edm_pairs`` -- packed squared-distance
                        matrix on the 2-simplex (Sec. I, II), FP64 loops.
 * ``at_energy`` / ``at_grad`` / ``at_grad_rows`` -- Axilrod-Teller triplet
                        energy (angle form) and its analytic gradient on the
                        3-simplex (Sec. I: triple-interaction n-body).
+* ``at_triplet_rows`` -- per-triplet Axilrod-Teller energies, packed.
 * ``lj_energy`` / ``lj_grad`` -- Lennard-Jones pair energy and gradient.
+* ``quad_contacts`` -- 4-point contacts (4-cliques of the contact graph) on
+                       the 4-simplex, by neighbour-list intersection.
 * ``checksum_range`` / ``checksum_walk`` -- element-id checksums.
 
 Only ``tests/``, ``__graft_entry__.smoke()`` and the benchmark's CPU-baseline
@@ -66,6 +71,8 @@ def lib():
         L.orc_lj_energy.argtypes = [_ptr, _i64, _i64, _dbl, _dbl, _dbl]
         L.orc_lj_energy.restype = _dbl
         L.orc_lj_grad.argtypes = [_ptr, _i64, _i64, _dbl, _dbl, _dbl, _ptr]
+        L.orc_quad_contacts.argtypes = [_ptr, _i64, _i64, _dbl]
+        L.orc_quad_contacts.restype = _i64
         L.orc_mix64.argtypes = [_u64]
         L.orc_mix64.restype = _u64
         L.orc_checksum_range.argtypes = [_u64]
@@ -161,6 +168,13 @@ def lj_grad(X: np.ndarray, eps: float = 1.0, sigma: float = 1.0, rc: float = 3.0
     G = np.empty((X.shape[0], 3), dtype=np.float64)
     lib().orc_lj_grad(X.ctypes.data, X.shape[0], X.shape[1], eps, sigma, rc, G.ctypes.data)
     return G
+
+
+def quad_contacts(X: np.ndarray, rc: float) -> int:
+    """Quadruplets i<j<k<l with all six pairs in contact (FP32 squared distance
+    below fl(rc^2)): the 4-cliques of the contact graph."""
+    X = _f32(X)
+    return int(lib().orc_quad_contacts(X.ctypes.data, X.shape[0], X.shape[1], rc))
 
 
 def mix64(x: int) -> int:

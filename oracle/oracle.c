@@ -1,8 +1,8 @@
 /*
  * FP64 CPU oracle -- TEST INFRASTRUCTURE ONLY.
  *
- * Plain nested loops over the discrete orthogonal 2-simplex (pairs) and
- * 3-simplex (triplets) in double precision.  It shares no code, header,
+ * Plain nested loops over the discrete orthogonal 2-simplex (pairs),
+ * 3-simplex (triplets) and 4-simplex (quadruplets) in double precision.  It shares no code, header,
  * table or constant with the HIP library; only tests, the smoke check and the
  * benchmark's CPU-baseline leg may load it.  No product path calls it.
  *
@@ -10,6 +10,7 @@
  *   EDM    : pairs i <= j < n           (n(n+1)/2 elements, diagonal included)
  *   LJ     : pairs i <  j < n           (n(n-1)/2 elements)
  *   AT     : triplets i < j < k < n     (n(n-1)(n-2)/6 elements)
+ *   K4     : quadruplets i < j < k < l  (n(n-1)(n-2)(n-3)/24 elements)
  *
  * Every function takes FP32 inputs exactly as the GPU reads them and promotes
  * each coordinate to double before any arithmetic.  Sums over OpenMP threads are
@@ -420,4 +421,71 @@ uint64_t orc_checksum_walk(int kind, int64_t n, int64_t *count)
     }
     if (count) *count = c;
     return s;
+}
+
+/* ------------------------------------------------------------------------ */
+/* 4-point contacts on the 4-simplex: the number of quadruplets i < j < k < l
+ * whose six pairs all lie within the contact radius rc (the 4-cliques of the
+ * contact graph; the 4-point analogue of the correlation counts the paper
+ * lists among simplex-shaped problems, Sec. I).  A pair is in contact when the
+ * FP32 squared distance s32 = fl(fma(dz,dz, fma(dy,dy, dx*dx))), d* = fl(x_j* -
+ * x_i*) for i < j, is below fl(rc*rc) -- the same decision rule as the LJ cutoff,
+ * so both sides decide every pair identically and the count is exact.
+ * Counting: forward neighbour lists N(i) = {j > i in contact} (sorted), then
+ * for every i, j in N(i) the common list C = N(i) & N(j), and for every k in C
+ * the size of C & N(k) (each l > k).                                         */
+static int64_t isect(const int32_t *a, int64_t na, const int32_t *b, int64_t nb, int32_t *out)
+{
+    int64_t i = 0, j = 0, c = 0;
+    while (i < na && j < nb) {
+        if (a[i] < b[j]) ++i;
+        else if (a[i] > b[j]) ++j;
+        else {
+            if (out) out[c] = a[i];
+            ++c; ++i; ++j;
+        }
+    }
+    return c;
+}
+
+int64_t orc_quad_contacts(const float *X, int64_t n, int64_t ldx, double rc)
+{
+    if (n < 4) return 0;
+    const float rc2 = (float)(rc * rc);
+    int64_t *start = (int64_t *)calloc((size_t)n + 1, sizeof(int64_t));
+    int64_t *deg = (int64_t *)calloc((size_t)n, sizeof(int64_t));
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t i = 0; i < n; ++i)
+        for (int64_t j = i + 1; j < n; ++j) deg[i] += lj_inside(X, ldx, i, j, rc2);
+    for (int64_t i = 0; i < n; ++i) start[i + 1] = start[i] + deg[i];
+    int32_t *adj = (int32_t *)malloc((size_t)(start[n] > 0 ? start[n] : 1) * sizeof(int32_t));
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t i = 0; i < n; ++i) {
+        int64_t c = start[i];
+        for (int64_t j = i + 1; j < n; ++j)
+            if (lj_inside(X, ldx, i, j, rc2)) adj[c++] = (int32_t)j;
+    }
+    int64_t total = 0;
+#pragma omp parallel reduction(+ : total)
+    {
+        int32_t *cij = (int32_t *)malloc((size_t)n * sizeof(int32_t));
+#pragma omp for schedule(dynamic, 4)
+        for (int64_t i = 0; i < n; ++i) {
+            const int32_t *ni = adj + start[i];
+            const int64_t di = deg[i];
+            for (int64_t a = 0; a < di; ++a) {
+                const int32_t j = ni[a];
+                const int64_t nc = isect(ni, di, adj + start[j], deg[j], cij);
+                for (int64_t b = 0; b < nc; ++b) {
+                    const int32_t k = cij[b];
+                    total += isect(cij, nc, adj + start[k], deg[k], NULL);
+                }
+            }
+        }
+        free(cij);
+    }
+    free(adj);
+    free(deg);
+    free(start);
+    return total;
 }

@@ -16,7 +16,7 @@ import torch
 
 __all__ = [
     "MAPS", "PRECS", "SmxError", "Pot", "lib", "volume", "parallel_blocks", "map_tiles_host",
-    "workspace_bytes", "simplex_map2", "simplex_map3", "simplex_map4", "simplex_count", "triplet_packed", "edm_packed", "triplet_energy",
+    "workspace_bytes", "simplex_map2", "simplex_map3", "simplex_map4", "simplex_count", "triplet_packed", "quad_contacts", "edm_packed", "triplet_energy",
     "triplet_energy_grad", "triplet_energy_backward", "TripletEnergy", "profile_enable",
     "profile_reset", "profile_read", "KERNELS",
 ]
@@ -27,7 +27,8 @@ LIB_PATH = os.path.join(_HERE, "libsmx.so")
 MAPS = {"lambda": 0, "bbox": 1, "linear": 2, "lambda_below": 3, "recursive": 4, "recursive_launch": 5}
 PRECS = {"fp32": 0, "bf16": 1, "split_bf16": 2}
 KERNELS = {"map2": 0, "map3": 1, "edm_diff": 2, "edm_gram": 3, "gram_prep": 4,
-           "triplet_energy": 5, "triplet_grad": 6, "lj": 7, "finalize": 8, "triplet_packed": 9, "map4": 10}
+           "triplet_energy": 5, "triplet_grad": 6, "lj": 7, "finalize": 8, "triplet_packed": 9, "map4": 10,
+           "quad_words": 11, "quad": 12}
 
 _i32, _i64, _sz, _vp, _dbl = ctypes.c_int, ctypes.c_int64, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_double
 
@@ -78,6 +79,7 @@ def lib():
             getattr(L, name).argtypes = [_i64, _i32, _i32, _i32, _vp, _vp, _vp, _sz, _vp]
         L.smx_simplex_count.argtypes = [_i32, _i64, _i32, _i32, _i32, _vp, _vp, _sz, _vp]
         L.smx_triplet_packed.argtypes = [_vp, _i64, _i64, _dbl, _i32, _vp, _vp, _sz, _vp, _vp]
+        L.smx_quad_contacts.argtypes = [_vp, _i64, _i64, _dbl, _i32, _vp, _vp, _sz, _vp, _vp]
         L.smx_edm_packed.argtypes = [_vp, _i64, _i64, _i64, _i32, _i32, _vp, _vp, _sz, _vp, _vp]
         L.smx_triplet_energy.argtypes = [_vp, _i64, _i64, ctypes.POINTER(_Pot), _i32, _vp, _vp, _sz, _vp, _vp]
         L.smx_triplet_energy_grad.argtypes = [_vp, _i64, _i64, ctypes.POINTER(_Pot), _i32, _vp, _vp, _vp,
@@ -247,6 +249,21 @@ def triplet_packed(X: torch.Tensor, nu: float = 1.0, map="lambda", stats=False, 
     _check(lib().smx_triplet_packed(xp, n, ldx, float(nu), _map(map), _ptr(E), _ptr(ws),
                                     0 if ws is None else ws.numel(), _ptr(s), _stream()))
     return (E, s) if stats else E
+
+
+def quad_contacts(X: torch.Tensor, rc: float, map="lambda", stats=False, out=None, ws=None):
+    """Number of quadruplets i < j < k < l with all six pairs in contact (FP32
+    squared distance below fl(rc^2)): int64 [1] on X's device; with stats=True
+    also the int64 [4] counters."""
+    xp, n, ldx = _xarg(X)
+    c = out if out is not None else torch.empty(1, dtype=torch.int64, device=X.device)
+    if c.dtype != torch.int64 or c.numel() < 1 or c.device != X.device:
+        raise ValueError("out must be an int64 tensor on X's device")
+    s = torch.zeros(4, dtype=torch.int64, device=X.device) if stats else None
+    ws = ws if ws is not None else _ws(workspace_bytes(3, n), X.device)
+    _check(lib().smx_quad_contacts(xp, n, ldx, float(rc), _map(map), _ptr(c), _ptr(ws), ws.numel(), _ptr(s),
+                                   _stream()))
+    return (c, s) if stats else c
 
 
 def triplet_energy_grad(X: torch.Tensor, pot: Pot = Pot(), map="lambda", ws=None):

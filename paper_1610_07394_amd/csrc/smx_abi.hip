@@ -192,6 +192,21 @@ static TripWs trip_ws(int64_t n) {
     return w;
 }
 
+struct QuadWs {
+    size_t cslots, sslots, words, total;
+    int64_t nb, npad;
+};
+static QuadWs quad_ws(int64_t n) {
+    QuadWs w{};
+    w.nb = (n + kQuadTile - 1) / kQuadTile;
+    w.npad = w.nb * kQuadTile;
+    w.cslots = 0;
+    w.sslots = kSlotBytes;
+    w.words = 2 * kSlotBytes;
+    w.total = align256(w.words + size_t(w.nb) * size_t(w.npad) * 8);
+    return w;
+}
+
 static inline hipStream_t S(void *s) { return reinterpret_cast<hipStream_t>(s); }
 
 }  // namespace smx
@@ -233,6 +248,7 @@ size_t smx_workspace_bytes(int op, int64_t n, int64_t d, int prec, int map) {
         return edm_ws(n, d, prec).total;
     }
     if (op == 2) return trip_ws(n).total;
+    if (op == 3) return quad_ws(n).total;
     return 0;
 }
 
@@ -443,6 +459,37 @@ int smx_triplet_energy_backward(const float *d_X, int64_t n, int64_t ldx, const 
                                 const double *d_gradE, float *d_dX, void *d_ws, size_t ws_bytes,
                                 void *stream) {
     return triplet_run(2, d_X, n, ldx, pot, map, nullptr, d_dX, d_gradE, d_ws, ws_bytes, nullptr, stream);
+}
+
+int smx_quad_contacts(const float *d_X, int64_t n, int64_t ldx, double rc, int map, int64_t *d_count,
+                      void *d_ws, size_t ws_bytes, int64_t *d_stats, void *stream) {
+    if (n < 0) return fail(SMX_EINVAL, "n must be >= 0");
+    if (n > 16384) return fail(SMX_EOVERFLOW, "n = %lld exceeds 16384", (long long)n);
+    if (ldx < 3) return fail(SMX_EINVAL, "ldx (%lld) < 3", (long long)ldx);
+    if (map < 0 || map > MAP_REC_LAUNCH) return fail(SMX_EINVAL, "unknown map %d", map);
+    if (map == MAP_BELOW) return fail(SMX_EUNSUPPORTED, "the from-below map is defined for m = 2 and 3 only");
+    if (!(rc >= 0.0) || !(rc < 1e18)) return fail(SMX_EINVAL, "rc must be finite and >= 0");
+    if (d_count == nullptr) return fail(SMX_EINVAL, "count must not be NULL");
+    if (n >= 4 && d_X == nullptr) return fail(SMX_EINVAL, "X must not be NULL");
+    const QuadWs w = quad_ws(n);
+    if (d_ws == nullptr || ws_bytes < w.total)
+        return fail(SMX_EINVAL, "workspace of %zu bytes required (got %zu)", w.total, ws_bytes);
+    MapGeom g2{}, g4{};
+    if (n >= 4 && (!make_geom(2, w.nb, map, g2) || !make_geom(4, w.nb, map, g4))) return g_status;
+    char *ws = reinterpret_cast<char *>(d_ws);
+    unsigned long long *cslots = reinterpret_cast<unsigned long long *>(ws + w.cslots);
+    unsigned long long *sslots = d_stats ? reinterpret_cast<unsigned long long *>(ws + w.sslots) : nullptr;
+    uint64_t *W = reinterpret_cast<uint64_t *>(ws + w.words);
+    int rc_;
+    if ((rc_ = launch_fill_u64(reinterpret_cast<uint64_t *>(ws), 2 * kSlotBytes / 8, S(stream)))) return rc_;
+    if (n >= 4) {
+        const float rc2 = float(rc * rc);
+        if ((rc_ = launch_contact_words(g2, d_X, n, ldx, rc2, W, w.npad, S(stream)))) return rc_;
+        if ((rc_ = launch_quad(g4, W, w.npad, n, cslots, sslots, S(stream)))) return rc_;
+    }
+    if ((rc_ = launch_count_finalize(cslots, d_count, S(stream)))) return rc_;
+    if (sslots) return launch_stats_finalize(sslots, g4.G, d_stats, S(stream));
+    return SMX_OK;
 }
 
 int smx_triplet_packed(const float *d_X, int64_t n, int64_t ldx, double nu, int map, float *d_E, void *d_ws,

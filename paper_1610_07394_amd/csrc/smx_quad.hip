@@ -1,0 +1,166 @@
+// 4-point contacts on the 4-simplex: the number of quadruplets i < j < k < l
+// whose six pairs all lie within a contact radius (the 4-cliques of the
+// contact graph) -- a 4-body count over the discrete orthogonal 4-simplex
+// (paper Sec. I lists correlation counts among simplex-shaped problems; the
+// 4-simplex parallel space is the lambda4 map built on the recursive set of
+// Sec. III-D).
+//
+// Two passes, both over simplex tiles of 64 elements per dimension:
+//   1. contact words (2-simplex, one 64-thread block per tile (X, Y), X <= Y):
+//      W[Y][64 X + p] bit q = contact(i, j), i = 64 X + p < j = 64 Y + q < n,
+//      decided on the FP32 squared distance fl(fma(dz,dz, fma(dy,dy, dx*dx))),
+//      d* = fl(x_j* - x_i*), below fl(rc*rc).  Column-tile-major, so the 64
+//      words of one tile pair are contiguous.
+//   2. cliques (4-simplex, one 256-thread block per tile X1 <= X2 <= X3 <= X4):
+//      the six 64-word blocks of the tile's index sets go to LDS; thread t takes
+//      p1 = t / 4 and sixteen p2, and for every contact (p1, p2) and every
+//      common neighbour p3 (bits of W13[p1] & W23[p2]) adds
+//      popcount(W14[p1] & W24[p2] & W34[p3]).  The ordering i < j < k < l within
+//      equal tiles and the bound n are already in the words.
+// Contacts are sparse, so a block does little arithmetic: the pass is bound by
+// how many blocks the map launches and by the 3 KB of words each block reads.
+#include "smx_device.h"
+#include "smx_internal.h"
+
+namespace smx {
+
+constexpr int kQuadWordThreads = 64;
+constexpr int kQuadThreads = 256;
+
+template <int MAP>
+__global__ __launch_bounds__(kQuadWordThreads) void contact_words_kernel(MapGeom g, const float *__restrict__ Xp,
+                                                                        int64_t n, int64_t ldx, float rc2,
+                                                                        uint64_t *__restrict__ W, int64_t npad) {
+    uint64_t lin;
+    int TX, TY;
+    if (!tile2_of<MAP, true>(g, lin, TX, TY)) return;
+    __shared__ float4 Pc[kQuadTile];
+    const int p = threadIdx.x;
+    const int64_t i = int64_t(TX) * kQuadTile + p, jc = int64_t(TY) * kQuadTile + p;
+    float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (jc < n) v = make_float4(Xp[jc * ldx + 0], Xp[jc * ldx + 1], Xp[jc * ldx + 2], 0.f);
+    Pc[p] = v;
+    float xi = 0.f, yi = 0.f, zi = 0.f;
+    if (i < n) {
+        xi = Xp[i * ldx + 0];
+        yi = Xp[i * ldx + 1];
+        zi = Xp[i * ldx + 2];
+    }
+    __syncthreads();
+    uint64_t word = 0;
+    if (i < n) {
+        const int64_t jbase = int64_t(TY) * kQuadTile;
+        const int q0 = TX == TY ? p + 1 : 0;
+        for (int q = q0; q < kQuadTile; ++q) {
+            const float4 c = Pc[q];
+            const float dx = c.x - xi, dy = c.y - yi, dz = c.z - zi;
+            const float s = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dx * dx));
+            if (jbase + q < n && s < rc2) word |= uint64_t(1) << q;
+        }
+    }
+    W[int64_t(TY) * npad + i] = word;
+}
+
+// Quadruplets i < j < k < l of a 4-simplex tile, in closed form (edge lengths
+// below n; runs of equal tile coordinates hold C(t, r) strict r-tuples).
+__device__ __forceinline__ uint64_t quad_tile_volume(const int T[4], int64_t n) {
+    uint64_t cnt = 1;
+    int d = 0;
+    while (d < 4) {
+        int r = 1;
+        while (d + r < 4 && T[d + r] == T[d]) ++r;
+        const int64_t rem = n - int64_t(T[d]) * kQuadTile;
+        const uint64_t t = rem <= 0 ? 0 : (rem < kQuadTile ? uint64_t(rem) : uint64_t(kQuadTile));
+        uint64_t v = 1;
+        for (int q = 0; q < r; ++q) v = t < uint64_t(q) ? 0 : v * (t - uint64_t(q)) / uint64_t(q + 1);
+        cnt *= v;
+        d += r;
+    }
+    return cnt;
+}
+
+template <int MAP, bool STATS>
+__global__ __launch_bounds__(kQuadThreads) void quad_kernel(MapGeom g, const uint64_t *__restrict__ W, int64_t npad,
+                                                           int64_t n, unsigned long long *cslots,
+                                                           unsigned long long *sslots) {
+    uint64_t lin;
+    int T[4];
+    if (!tile4_of<MAP, true>(g, lin, T)) return;
+    // pair sets s = (a, b): 0 (0,1), 1 (0,2), 2 (0,3), 3 (1,2), 4 (1,3), 5 (2,3)
+    __shared__ uint64_t A[6][kQuadTile];
+    __shared__ unsigned long long red[kQuadThreads / kWave];
+    const int t = threadIdx.x;
+    const int64_t T0 = T[0], T1 = T[1], T2 = T[2], T3 = T[3];
+    for (int e = t; e < 6 * kQuadTile; e += kQuadThreads) {
+        const int s = e >> 6, p = e & (kQuadTile - 1);
+        const int64_t ra = s < 3 ? T0 : (s < 5 ? T1 : T2);
+        const int64_t cb = s == 0 ? T1 : (s == 1 || s == 3) ? T2 : T3;
+        A[s][p] = W[cb * npad + ra * kQuadTile + p];
+    }
+    __syncthreads();
+    const int p1 = t >> 2, p2b = (t & 3) << 4;
+    const uint64_t a02 = A[1][p1], a03 = A[2][p1];
+    uint32_t bits = uint32_t(A[0][p1] >> p2b) & 0xFFFFu;
+    uint32_t cnt = 0;
+    while (bits != 0) {
+        const int p2 = p2b + __builtin_ctz(bits);
+        bits &= bits - 1u;
+        uint64_t m3 = a02 & A[3][p2];
+        const uint64_t w = a03 & A[4][p2];
+        while (m3 != 0) {
+            const int p3 = __builtin_ctzll(m3);
+            m3 &= m3 - 1;
+            cnt += uint32_t(__builtin_popcountll(w & A[5][p3]));
+        }
+    }
+    const unsigned long long c = block_sum<unsigned long long, kQuadThreads>(cnt, red);
+    if (t == 0) {
+        if (c != 0) atomicAdd(cslots + (lin % kSlots) * kSlotStride, c);
+        if (STATS) stats_add(sslots, lin, quad_tile_volume(T, n), 0);
+    }
+}
+
+__global__ void count_finalize_kernel(const unsigned long long *slots, int64_t *out) {
+    __shared__ unsigned long long red[kSlots / kWave];
+    const unsigned long long v = block_sum<unsigned long long, kSlots>(slots[threadIdx.x * kSlotStride], red);
+    if (threadIdx.x == 0) out[0] = int64_t(v);
+}
+
+int launch_contact_words(const MapGeom &g, const float *X, int64_t n, int64_t ldx, float rc2, uint64_t *W,
+                         int64_t npad, hipStream_t s) {
+    prof_begin(K_QUAD_WORDS, s);
+    for_each_launch(g, [&](auto M, const MapGeom &gg) {
+        constexpr int MAPK = decltype(M)::value;
+        const dim3 grid = MAPK == MAP_BBOX ? dim3(gg.nb, gg.nb, 1) : grid_for(gg.G, kQuadWordThreads);
+        hipLaunchKernelGGL((contact_words_kernel<MAPK>), grid, dim3(kQuadWordThreads), 0, s, gg, X, n, ldx, rc2, W,
+                           npad);
+    });
+    prof_end(K_QUAD_WORDS, s);
+    return check_launch("contact words");
+}
+
+int launch_quad(const MapGeom &g, const uint64_t *W, int64_t npad, int64_t n, unsigned long long *cslots,
+                unsigned long long *sslots, hipStream_t s) {
+    prof_begin(K_QUAD, s);
+    for_each_launch(g, [&](auto M, const MapGeom &gg) {
+        constexpr int MAPK = decltype(M)::value;
+        const dim3 grid = grid_for(gg.G, kQuadThreads);
+        if (sslots)
+            hipLaunchKernelGGL((quad_kernel<MAPK, true>), grid, dim3(kQuadThreads), 0, s, gg, W, npad, n, cslots,
+                               sslots);
+        else
+            hipLaunchKernelGGL((quad_kernel<MAPK, false>), grid, dim3(kQuadThreads), 0, s, gg, W, npad, n, cslots,
+                               sslots);
+    });
+    prof_end(K_QUAD, s);
+    return check_launch("quad contacts");
+}
+
+int launch_count_finalize(const unsigned long long *slots, int64_t *out, hipStream_t s) {
+    prof_begin(K_FINALIZE, s);
+    hipLaunchKernelGGL(count_finalize_kernel, dim3(1), dim3(kSlots), 0, s, slots, out);
+    prof_end(K_FINALIZE, s);
+    return check_launch("count finalize");
+}
+
+}  // namespace smx

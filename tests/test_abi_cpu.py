@@ -147,6 +147,17 @@ def test_validation_errors_before_any_device_work():
     assert L.smx_triplet_packed(null, 10, 3, 1.0, 0, null, null, 0, null, null) == 1
     assert L.smx_triplet_packed(ctypes.c_void_p(256), 10, 3, 1.0, 0, ctypes.c_void_p(256), null, 0,
                                 ctypes.c_void_p(256), null) == 1
+    # 4-point contacts: n past 16384, bad ldx / map / rc, from below, NULL count, no workspace
+    assert L.smx_quad_contacts(null, 16385, 3, 1.0, 0, null, null, 0, null, null) == 2
+    assert L.smx_quad_contacts(null, 10, 2, 1.0, 0, null, null, 0, null, null) == 1
+    assert L.smx_quad_contacts(null, 10, 3, 1.0, 9, null, null, 0, null, null) == 1
+    assert L.smx_quad_contacts(null, 10, 3, 1.0, 3, null, null, 0, null, null) == 3
+    assert L.smx_quad_contacts(null, 10, 3, -1.0, 0, null, null, 0, null, null) == 1
+    assert L.smx_quad_contacts(null, 10, 3, float("nan"), 0, null, null, 0, null, null) == 1
+    assert L.smx_quad_contacts(ctypes.c_void_p(256), 10, 3, 1.0, 0, null, null, 0, null, null) == 1
+    assert L.smx_quad_contacts(ctypes.c_void_p(256), 10, 3, 1.0, 0, ctypes.c_void_p(256), null, 0, null,
+                               null) == 1
+    assert b"workspace" in L.smx_last_error()
     # EDM argument checks
     assert L.smx_edm_packed(null, 10, 0, 3, 0, 0, null, null, 0, null, null) == 1
     assert L.smx_edm_packed(null, 10, 3, 2, 0, 0, null, null, 0, null, null) == 1

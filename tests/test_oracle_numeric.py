@@ -272,3 +272,55 @@ def test_checksum_walk_pure_python():
                     s = (s + oracle.mix64(l * (l - 1) * (l - 2) * (l - 3) // 24 + k * (k - 1) * (k - 2) // 6
                                           + j * (j - 1) // 2 + i)) % M
     assert oracle.checksum_walk("quads_lt", n)[0] == s
+
+
+# --------------------------------------------------------------------------
+# 4-point contacts (4-cliques of the contact graph) on the 4-simplex.
+def _contacts_brute(X, rc2):
+    """All quadruplets by four nested loops.  The inputs lie on a grid of
+    step 1/4, so every squared distance is exact in FP32 and FP64 alike and
+    the contact test needs no rounding."""
+    X = np.asarray(X, dtype=np.float64)
+    n = X.shape[0]
+    adj = ((X[:, None, :] - X[None, :, :]) ** 2).sum(-1) < rc2
+    c = 0
+    for i in range(n):
+        for j in range(i + 1, n):
+            if not adj[i, j]:
+                continue
+            for k in range(j + 1, n):
+                if not (adj[i, k] and adj[j, k]):
+                    continue
+                for l in range(k + 1, n):
+                    c += bool(adj[i, l] and adj[j, l] and adj[k, l])
+    return c
+
+
+@pytest.mark.parametrize("n,seed", [(4, 1), (12, 2), (25, 3), (40, 4)])
+def test_quad_contacts_brute_force(n, seed):
+    X = synth.integer(n, 3, seed=seed, lo=0, hi=12).astype(np.float32) * np.float32(0.25)
+    for m in (0, 10, 20, 40, 80, 10000):  # rc^2 = m/16 + 1/32: never equal to a squared distance
+        rc2 = m / 16 + 1 / 32
+        assert oracle.quad_contacts(X, rc2 ** 0.5) == _contacts_brute(X, rc2)
+
+
+def test_quad_contacts_closed_forms():
+    # everything in contact: C(n, 4); nothing: 0
+    X = synth.uniform(30, 3, seed=9)
+    assert oracle.quad_contacts(X, 10.0) == math.comb(30, 4)
+    assert oracle.quad_contacts(X, 0.0) == 0
+    # points 1 apart on a line, contact below 3.5: exactly the n - 3 runs of four
+    L = np.zeros((50, 3), np.float32)
+    L[:, 0] = np.arange(50)
+    assert oracle.quad_contacts(L, 3.5) == 47
+    assert oracle.quad_contacts(L, 2.5) == 0
+    # cube corners, contact below 1.01 sqrt(2) (no body diagonal): one corner
+    # of each antipodal pair, 2^4 = 16 (6 faces, 2 tetrahedra, 8 vertex stars)
+    C = np.array([[x, y, z] for x in (0, 1) for y in (0, 1) for z in (0, 1)], np.float32)
+    assert oracle.quad_contacts(C, 1.01 * 2 ** 0.5) == 16
+    assert oracle.quad_contacts(C, 1.01) == 0
+    assert oracle.quad_contacts(C, 1.8) == math.comb(8, 4)
+    # invariant under a relabelling of the points
+    X = synth.uniform(60, 3, seed=5) * np.float32(4.0)
+    p = np.random.default_rng(0).permutation(60)
+    assert oracle.quad_contacts(X[p], 1.5) == oracle.quad_contacts(X, 1.5) > 0
