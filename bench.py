@@ -254,7 +254,7 @@ def main():
             q_ms, q_c = smx.profile_read("quad")
             smx.profile_enable(False)
             qd[kind] = {"words_ms": w_ms / w_c, "quad_ms": q_ms / q_c,
-                        "blocks": smx.parallel_blocks(4, N_AT, 64, kind)}
+                        "blocks": smx.parallel_blocks(4, -(-N_AT // 64), 1, kind)}
         nq = math.comb(N_AT, 4)
         t = (qd["lambda"]["words_ms"] + qd["lambda"]["quad_ms"]) / 1e3
         comps["quad_contacts_n8192"] = {

@@ -34,7 +34,7 @@ def test_contacts_vs_oracle_all_maps(n):
             assert int(c.item()) == ref, (kind, rc)
             nb = -(-n // 64)
             assert int(s[0]) == math.comb(n, 4) and int(s[2]) == math.comb(nb + 3, 4)
-            assert int(s[3]) == smx.parallel_blocks(4, n, 64, kind)
+            assert int(s[3]) == smx.parallel_blocks(4, nb, 1, kind)
 
 
 @pytest.mark.parametrize("n", [0, 1, 2, 3])
