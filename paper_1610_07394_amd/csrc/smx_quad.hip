@@ -83,13 +83,33 @@ template <int MAP, bool STATS>
 __global__ __launch_bounds__(kQuadThreads) void quad_kernel(MapGeom g, const uint64_t *__restrict__ W, int64_t npad,
                                                            int64_t n, unsigned long long *cslots,
                                                            unsigned long long *sslots) {
-    uint64_t lin;
-    int T[4];
-    if (!tile4_of<MAP, true>(g, lin, T)) return;
     // pair sets s = (a, b): 0 (0,1), 1 (0,2), 2 (0,3), 3 (1,2), 4 (1,3), 5 (2,3)
     __shared__ uint64_t A[6][kQuadTile];
     __shared__ unsigned long long red[kQuadThreads / kWave];
+    __shared__ int tileS[5];
+    __shared__ uint64_t linS;
     const int t = threadIdx.x;
+    // A block does little work, so its map evaluation shows: the first wave
+    // evaluates it once for the block.  No XCD renumbering: the 4-simplex maps
+    // leave their filtered blocks in long runs (the tail of each lambda4 node),
+    // which contiguous per-XCD ranges would hand to a few XCDs only.
+    if (t < kWave) {
+        uint64_t l;
+        int Tw[4];
+        const bool ok = tile4_of<MAP, false>(g, l, Tw);
+        if (t == 0) {
+            tileS[0] = Tw[0];
+            tileS[1] = Tw[1];
+            tileS[2] = Tw[2];
+            tileS[3] = Tw[3];
+            tileS[4] = ok;
+            linS = l;
+        }
+    }
+    __syncthreads();
+    if (!tileS[4]) return;
+    const int T[4] = {tileS[0], tileS[1], tileS[2], tileS[3]};
+    const uint64_t lin = linS;
     const int64_t T0 = T[0], T1 = T[1], T2 = T[2], T3 = T[3];
     for (int e = t; e < 6 * kQuadTile; e += kQuadThreads) {
         const int s = e >> 6, p = e & (kQuadTile - 1);
