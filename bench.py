@@ -45,6 +45,8 @@ N_EDM, D_EDM = 65536, 64
 N_GRAM, D_GRAM = 32768, 512
 N_AT = 8192
 N_MAP4 = 1024  # 4-simplex map-only comparison: 8^4-element tiles, nb = 128
+ALL_MAPS = ("lambda", "bbox", "linear", "recursive", "recursive_launch")
+QUICK_MAPS = ("lambda", "bbox")
 QUAD_RC = 2.0  # contact radius of the 4-point contact count (mean contact degree ~34)
 
 
@@ -55,6 +57,9 @@ def parse():
     p.add_argument("--warmup", type=int, default=2)
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-compare", action="store_true")
+    p.add_argument("--quick-compare", action="store_true",
+                   help="compare lambda with the bounding box only (no linear / recursive maps, no map-only "
+                        "parallel spaces): a short run for tracing")
     p.add_argument("--only", default="", help="comma list of edm,gram,at (default all)")
     p.add_argument("--calibrate-copy", action="store_true",
                    help="first run one 1 GiB device-to-device copy (known traffic) to scale "
@@ -243,7 +248,7 @@ def main():
         qd = {}
         ws4 = torch.empty(smx.workspace_bytes(3, N_AT), dtype=torch.uint8, device=dev)
         cnt = torch.empty(1, dtype=torch.int64, device=dev)
-        for kind in ("lambda", "bbox", "linear", "recursive", "recursive_launch"):
+        for kind in QUICK_MAPS if args.quick_compare else ALL_MAPS:
             smx.quad_contacts(X5, QUAD_RC, kind, out=cnt, ws=ws4)
             torch.cuda.synchronize()
             smx.profile_enable(True)
@@ -294,7 +299,7 @@ def main():
     compare = None
     if not args.no_compare:
         compare = {}
-        for kind in ("bbox", "linear", "recursive", "recursive_launch"):
+        for kind in (QUICK_MAPS if args.quick_compare else ALL_MAPS)[1:]:
             step(kind)  # warm
             torch.cuda.synchronize()
             smx.profile_enable(True)
@@ -305,7 +310,7 @@ def main():
             smx.profile_enable(False)
             compare[kind] = {k: (v[0] / v[1] if v[1] else None) for k, v in kk.items()}
         compare["lambda"] = {k: kavg[k] for k in ("edm_diff", "edm_gram", "triplet_grad", "lj")}
-        for base in ("bbox", "recursive", "recursive_launch"):
+        for base in ("bbox",) if args.quick_compare else ("bbox", "recursive", "recursive_launch"):
             sp = {}
             for k in ("edm_diff", "edm_gram", "triplet_grad"):
                 if compare[base].get(k) and compare["lambda"].get(k):
@@ -316,7 +321,7 @@ def main():
         # checksum); "count" = each mapped block adds its tile's closed-form
         # count, so the time is the map plus the launched blocks alone.
         mo = {}
-        for kind in ("lambda", "bbox", "linear", "lambda_below", "recursive", "recursive_launch"):
+        for kind in () if args.quick_compare else ("lambda", "bbox", "linear", "lambda_below", "recursive", "recursive_launch"):
             for m, n, rho in ((2, N_EDM, 16), (3, N_AT, 8), (4, N_MAP4, 8)):
                 if m == 4 and kind == "lambda_below":
                     continue  # not defined for the 4-simplex
