@@ -481,11 +481,54 @@ SMX_HD bool cube4(uint32_t id, const MapGeom &g, int X[4]) {
 // b^2 (b+1)(7b-1)/12 <= b^4 tiles.  Each node owns one b^4 orthotope of blocks:
 // level l (b = nb'/2^(l+1)) holds 2^l nodes, 2^(4 lg - 3l - 4) blocks, and the
 // levels add up to (nb'^4 - nb')/14.  Within a node the leading blocks unrank
-// R3, R2, R1 in turn (the sorted triples and pairs by the exact-root linear
-// maps above, the free coordinate fastest); the rest are filtered (the 5/7
+// R3, R2, R1 in turn (the sorted triples and pairs by FP32 roots with exact
+// 32-bit corrections, the free coordinate fastest); the rest are filtered (the 5/7
 // extra volume of the set).  Blocks past the orthotopes form a lambda3 grid over
 // nb whose tile (X, Y, Z) becomes (X, Y, Z, Z).  The level is found in at most
 // lg block-uniform steps.
+// Unranking inside a lambda4 node (ranks below 2^27, values below 2^8): an
+// FP32 estimate, then exact 32-bit corrections.  tri32: largest y with
+// y(y+1)/2 <= k; tet32: largest z with z(z+1)(z+2)/6 <= k; quo32: floor(k / q).
+SMX_HD uint32_t tri32(uint32_t k) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    const float f = __builtin_sqrtf(8.0f * float(k) + 1.0f);
+#else
+    const float f = std::sqrt(8.0f * float(k) + 1.0f);
+#endif
+    uint32_t y = uint32_t((f - 1.0f) * 0.5f);
+    while (y > 0 && y * (y + 1) / 2 > k) --y;
+    while ((y + 1) * (y + 2) / 2 <= k) ++y;
+    return y;
+}
+
+SMX_HD uint32_t tet32(uint32_t k) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    // 6k to the power 1/3 by the hardware base-2 logarithm and exponential
+    const float f = __builtin_amdgcn_exp2f(__builtin_amdgcn_logf(6.0f * float(k) + 1.0f) * (1.0f / 3.0f));
+#else
+    const float f = std::cbrt(6.0f * float(k) + 1.0f);
+#endif
+    uint32_t z = f > 1.0f ? uint32_t(f) - 1 : 0;
+    while (z > 0 && z * (z + 1) * (z + 2) / 6 > k) --z;
+    while ((z + 1) * (z + 2) * (z + 3) / 6 <= k) ++z;
+    return z;
+}
+
+SMX_HD uint32_t quo32(uint32_t k, uint32_t q) {
+    uint32_t p = uint32_t(float(k) / float(q));
+    while (p > 0 && p * q > k) --p;
+    while ((p + 1) * q <= k) ++p;
+    return p;
+}
+
+// Sorted triple x <= y <= z of rank t (listed by z, then y, then x).
+SMX_HD void unrank3(uint32_t t, uint32_t &x, uint32_t &y, uint32_t &z) {
+    z = tet32(t);
+    const uint32_t r = t - z * (z + 1) * (z + 2) / 6;
+    y = tri32(r);
+    x = r - y * (y + 1) / 2;
+}
+
 SMX_HD uint64_t lambda4_main_blocks(int lg) {
     uint64_t v = 0;
     for (int l = 0; l < lg; ++l) v += uint64_t(1) << (4 * lg - 3 * l - 4);
@@ -514,37 +557,35 @@ SMX_HD bool lambda4(uint32_t id, int lg, int nb, uint32_t main, int X[4]) {
     const uint32_t b = 1u << h;
     const uint32_t o = (r >> (4 * h)) << (h + 1);
     uint32_t loc = r & ((1u << (4 * h)) - 1u);
-    int t[3];
+    uint32_t x, y, z;
     const uint32_t n3 = b * (b * (b + 1) * (b + 2) / 6);
     if (loc < n3) {
-        linear3(loc >> h, t[0], t[1], t[2]);
-        X[0] = int(o) + t[0];
-        X[1] = int(o) + t[1];
-        X[2] = int(o) + t[2];
+        unrank3(loc >> h, x, y, z);
+        X[0] = int(o + x);
+        X[1] = int(o + y);
+        X[2] = int(o + z);
         X[3] = int(o + b + (loc & (b - 1u)));
         return X[3] < nb;
     }
     loc -= n3;
     const uint32_t P = b * (b + 1) / 2, Q = b * (b - 1) / 2;
     if (loc < P * Q) {
-        const uint32_t p = loc / Q, s = loc - p * Q;
-        int a, c;
-        linear2(p, a, c);
-        const uint32_t y = tri_root(s);  // strict pair (d < e): e = y + 1, d = s - y(y+1)/2
-        X[0] = int(o) + a;
-        X[1] = int(o) + c;
-        X[2] = int(o + b + (s - y * (y + 1) / 2));
-        X[3] = int(o + b + y + 1);
+        const uint32_t p = quo32(loc, Q), s = loc - p * Q;
+        const uint32_t c = tri32(p), e1 = tri32(s);  // (a <= c) of rank p; strict (d < e) of rank s: e = e1 + 1
+        X[0] = int(o + (p - c * (c + 1) / 2));
+        X[1] = int(o + c);
+        X[2] = int(o + b + (s - e1 * (e1 + 1) / 2));
+        X[3] = int(o + b + e1 + 1);
         return X[3] < nb;
     }
     loc -= P * Q;
     const uint32_t n1 = b * ((b + 1) * b * (b - 1) / 6);
     if (loc < n1) {
-        linear3(loc >> h, t[0], t[1], t[2]);  // X2 <= X3 <= X4 - 1 in H
+        unrank3(loc >> h, x, y, z);  // X2 <= X3 <= X4 - 1 in H
         X[0] = int(o + (loc & (b - 1u)));
-        X[1] = int(o + b) + t[0];
-        X[2] = int(o + b) + t[1];
-        X[3] = int(o + b) + t[2] + 1;
+        X[1] = int(o + b + x);
+        X[2] = int(o + b + y);
+        X[3] = int(o + b + z + 1);
         return X[3] < nb;
     }
     return false;
