@@ -1,0 +1,101 @@
+// Host build of the library's block-space maps (the same inline header the
+// kernels use), for running under AddressSanitizer and UndefinedBehaviorSanitizer:
+// every block of every map is decoded for a range of nb, and the mapped tiles
+// must cover the target simplex exactly once, with no shift, overflow or
+// out-of-range access along the way.  Exit status 0 and "ok" on success.
+#include <cstdio>
+#include <cstdlib>
+#include <vector>
+
+#include "smx_maps.h"
+
+using namespace smx;
+
+static long long binom(long long n, int k) {
+    long long v = 1;
+    for (int i = 0; i < k; ++i) v = v * (n - i) / (i + 1);
+    return v;
+}
+
+// rank of a sorted tuple in [0, nb)^m (colex), for the visited bitmap
+static long long rank_tuple(const int *t, int m) {
+    long long r = 0;
+    for (int d = 0; d < m; ++d) r += binom(t[d] + d, d + 1);
+    return r;
+}
+
+static int fails = 0;
+
+static void check(int m, int nb, int map) {
+    const int lg = ceil_log2_u64(uint64_t(nb));
+    uint64_t G = 0;
+    uint32_t main = 0;
+    if (map == MAP_LAMBDA) {
+        if (m == 2) G = lambda2_blocks(lg);
+        if (m == 3) { main = lambda3_main_blocks(lg); G = main + lambda2_blocks(lg); }
+        if (m == 4) { main = uint32_t(lambda4_main_blocks(lg)); G = main + lambda3_main_blocks(lg) + lambda2_blocks(lg); }
+    } else if (map == MAP_REC) {
+        G = rec_blocks(m, lg);
+    } else if (map == MAP_BELOW) {
+        G = m == 2 ? below2_blocks(uint64_t(nb)) : below3_blocks(uint64_t(nb));
+    } else {  // linear
+        G = uint64_t(binom(nb + m - 1, m));
+    }
+    const long long target = binom(nb + m - 1, m);
+    std::vector<unsigned char> seen(size_t(target), 0);
+    long long mapped = 0;
+    for (uint64_t id = 0; id < G; ++id) {
+        int t[4] = {0, 0, 0, 0};
+        bool ok = false;
+        if (m == 2) {
+            if (map == MAP_LAMBDA) ok = lambda2(uint32_t(id), lg, nb, t[0], t[1]);
+            else if (map == MAP_REC) ok = rec2(uint32_t(id), lg, nb, uint32_t(G), t[0], t[1]);
+            else if (map == MAP_BELOW) ok = below2(id, uint32_t(nb), t[0], t[1]);
+            else { linear2(uint32_t(id), t[0], t[1]); ok = true; }
+        } else if (m == 3) {
+            if (map == MAP_LAMBDA) ok = lambda3(uint32_t(id), lg, nb, main, t[0], t[1], t[2]);
+            else if (map == MAP_REC) ok = rec3(uint32_t(id), lg, nb, uint32_t(G), t[0], t[1], t[2]);
+            else if (map == MAP_BELOW) ok = below3(id, uint32_t(nb), t[0], t[1], t[2]);
+            else { linear3(uint32_t(id), t[0], t[1], t[2]); ok = true; }
+        } else {
+            if (map == MAP_LAMBDA) ok = lambda4(uint32_t(id), lg, nb, main, t);
+            else if (map == MAP_REC) ok = rec4(uint32_t(id), lg, nb, uint32_t(G), t);
+            else { linear4(uint32_t(id), t); ok = true; }
+        }
+        if (!ok) continue;
+        for (int d = 0; d < m; ++d) {
+            const bool bad = t[d] < 0 || t[d] >= nb || (d > 0 && t[d] < t[d - 1]);
+            if (bad) {
+                if (fails++ < 10) std::printf("m=%d nb=%d map=%d block %llu: tile out of the simplex\n", m, nb, map,
+                                              (unsigned long long)id);
+                ok = false;
+                break;
+            }
+        }
+        if (!ok) continue;
+        const long long r = rank_tuple(t, m);
+        if (seen[size_t(r)]++) {
+            if (fails++ < 10) std::printf("m=%d nb=%d map=%d: tile mapped twice\n", m, nb, map);
+        }
+        ++mapped;
+    }
+    if (mapped != target && fails++ < 10)
+        std::printf("m=%d nb=%d map=%d: %lld of %lld tiles mapped\n", m, nb, map, mapped, target);
+}
+
+int main() {
+    const int maps2[] = {MAP_LAMBDA, MAP_LINEAR, MAP_BELOW, MAP_REC};
+    for (int nb = 1; nb <= 300; nb += (nb < 40 ? 1 : 37))
+        for (int map : maps2) check(2, nb, map);
+    for (int nb = 1; nb <= 80; nb += (nb < 24 ? 1 : 13))
+        for (int map : maps2) check(3, nb, map);
+    const int maps4[] = {MAP_LAMBDA, MAP_LINEAR, MAP_REC};
+    for (int nb = 1; nb <= 40; nb += (nb < 12 ? 1 : 9))
+        for (int map : maps4) check(4, nb, map);
+    if (fails) {
+        std::printf("%d failures\n", fails);
+        return 1;
+    }
+    std::printf("ok\n");
+    return 0;
+}
