@@ -5,6 +5,7 @@ hand-derived tables in tests/golden, brute-force set equality with the target
 simplices, the recursive orthotope sets of Sec. III (built here by recursion,
 without any log2 / clz), and the closed-form volumes of Sec. I and III.
 """
+import math
 import os
 from fractions import Fraction
 from math import comb, factorial
@@ -411,3 +412,99 @@ def test_recursive4_counts(k):
     n = 2 ** k
     assert maps.recursive_tiles(4, n).shape[0] == _vol_rec(n, 4, 4) + 4 ** k
     assert maps.recursive_sub_maps(4, n) == (4 ** (k + 1) - 1) // 3
+
+
+# --------------------------------------------------------------------------
+# Closed-form inverses, derived from the recursive sets rather than from the
+# forward maps: a tile of T2 with X < Y belongs to the level b = 2^L where
+# L = msb(X xor Y) (the highest bit where the two indices first part) and to
+# the square q = X >> (L+1) of that level.
+def _msb(v):
+    return np.array([int(x).bit_length() - 1 for x in v], dtype=np.int64)
+
+
+@pytest.mark.parametrize("nb", [2, 4, 8, 64, 256])
+def test_lambda2_closed_form_inverse(nb):
+    t = maps.lambda2_tiles(nb)
+    ex, _ = maps.pi2_extent(nb)
+    wy, wx = np.divmod(np.arange(t.shape[0], dtype=np.int64), ex)
+    X, Y = t[:, 0], t[:, 1]
+    off = X < Y
+    L = _msb(X[off] ^ Y[off])
+    b = np.int64(1) << L
+    q = X[off] >> (L + 1)
+    np.testing.assert_array_equal(X[off] - q * b, wx[off])
+    np.testing.assert_array_equal(Y[off] - 2 * q * b, wy[off])
+    diag = X == Y
+    low = X[diag] < nb // 2
+    np.testing.assert_array_equal(np.where(low, 0, nb), wy[diag])
+    np.testing.assert_array_equal(np.where(low, X[diag], X[diag] - nb // 2), wx[diag])
+
+
+@pytest.mark.parametrize("nb", [4, 8, 32, 64])
+def test_lambda3_closed_form_inverse(nb):
+    """Tiles X <= Y < Z of the orthotope part: level L = msb(X xor Z), offset
+    o = X with the low L+1 bits cleared; Y >= o + b is the first prism."""
+    t = maps.lambda3_main_tiles(nb)
+    ex, ey, _ = maps.pi3_extent(nb)
+    idx = np.arange(t.shape[0], dtype=np.int64)
+    wx, wy, wz = idx % ex, (idx // ex) % ey, idx // (ex * ey)
+    ok = t[:, 0] >= 0
+    X, Y, Z = t[ok, 0], t[ok, 1], t[ok, 2]
+    L = _msb(X ^ Z)
+    b = np.int64(1) << L
+    o = (X >> (L + 1)) << (L + 1)
+    first = Y >= o + b
+    u = np.where(first, X - o, Z - o - b)
+    v = np.where(first, Y - o - b, Y - o)
+    w = np.where(first, Z - o - b, X - o)
+    half = nb // 2
+    main = b == half
+    q = o // (2 * b)
+    np.testing.assert_array_equal(np.where(main, u, u + q * b), wx[ok])
+    np.testing.assert_array_equal(np.where(main, v, v + b), wy[ok])
+    np.testing.assert_array_equal(np.where(main, w, w + half), wz[ok])
+
+
+# --------------------------------------------------------------------------
+# Sec. III-D, choosing (r, beta): V(S_n) = (n^m - beta^(log_{1/r} n)) /
+# (1/r^m - beta) (the paper's generic closed form).  With 1/r^m - beta equal to
+# m! exactly, V(S_n) < n^m / m! < C(n+m-2, m) = V(Delta_{n-1}) for every n >= 2
+# and m >= 4 (the simplex has a positive n^(m-1) term), so the set never covers;
+# approaching m! from below, 1/r^m - beta = m! - eps, it covers from some n0,
+# and n0 grows as eps shrinks.
+def _vol_generic(n, m, beta, inv_rm):
+    depth = math.log(n) / math.log(inv_rm ** (1.0 / m))  # log_{1/r} n
+    return (n ** m - beta ** depth) / (inv_rm - beta)
+
+
+def _n0(m, beta, eps, limit=2 ** 24):
+    inv_rm = math.factorial(m) + beta - eps
+    n0 = None
+    for k in range(1, 25):
+        for n in (2 ** k, 3 * 2 ** (k - 1)):
+            if n > limit:
+                continue
+            covers = _vol_generic(n, m, beta, inv_rm) >= comb(n + m - 2, m)
+            if covers and n0 is None:
+                n0 = n
+            if not covers:
+                n0 = None
+    return n0
+
+
+@pytest.mark.parametrize("m", [4, 5, 6, 7])
+def test_generic_set_with_exact_factorial_never_covers(m):
+    for beta in (2, 3, 4):
+        inv_rm = math.factorial(m) + beta
+        for n in [2, 3, 5, 10, 100, 1000, 10 ** 4, 10 ** 5]:
+            assert _vol_generic(n, m, beta, inv_rm) < comb(n + m - 2, m)
+
+
+def test_generic_set_from_below_covers_beyond_n0():
+    for m in (4, 5):
+        n_prev = 0
+        for eps in (4.0, 1.0, 0.25):
+            n0 = _n0(m, 2, eps)
+            assert n0 is not None and n0 > n_prev  # a finite n0, growing as eps -> 0
+            n_prev = n0
