@@ -286,6 +286,18 @@ int smx_triplet_packed(const float *d_X, int64_t n, int64_t ldx, double nu, int 
 int smx_quad_contacts(const float *d_X, int64_t n, int64_t ldx, double rc, int map, int64_t *d_count,
                       void *d_ws, size_t ws_bytes, int64_t *d_stats, void *stream);
 
+/* Device checks.  The library can be built a second time with SMX_CHECKED=1
+ * (libsmx_checked.so, same ABI): every map evaluation then verifies that its
+ * tile lies in the simplex, and every unmasked store on a tile taken for
+ * interior verifies that its element does; a violation skips the access and
+ * sets a flag bit (1: a map left the simplex, 2: a store left it).  Callers
+ * that want a map or a kernel checked run it through that library and read
+ * the flags here, which synchronises with the device.
+ *   flags  host uint32 out: the OR of the flags of all kernels.
+ *   clear  != 0: reset the flags after reading them.
+ * SMX_EUNSUPPORTED in the normal library (no checks compiled in). */
+int smx_check_flags(uint32_t *flags, int clear);
+
 /* d_out[q] = gradE[0] * d_G[q] for q < 3n (FP32 out, FP64 scale): the backward
  * pass of smx_triplet_energy_grad's output, given the incoming gradient
  * d_gradE (FP64 device scalar).  d_out may alias d_G. */

@@ -18,11 +18,13 @@ __all__ = [
     "MAPS", "PRECS", "SmxError", "Pot", "lib", "volume", "parallel_blocks", "map_tiles_host",
     "workspace_bytes", "simplex_map2", "simplex_map3", "simplex_map4", "simplex_count", "triplet_packed", "quad_contacts", "edm_packed", "triplet_energy",
     "triplet_energy_grad", "triplet_energy_backward", "TripletEnergy", "profile_enable",
-    "profile_reset", "profile_read", "KERNELS",
+    "profile_reset", "profile_read", "KERNELS", "select_library", "check_flags",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libsmx.so")
+# the same library with device checks compiled in (see smx_check_flags)
+LIB_CHECKED_PATH = os.path.join(_HERE, "libsmx_checked.so")
 
 MAPS = {"lambda": 0, "bbox": 1, "linear": 2, "lambda_below": 3, "recursive": 4, "recursive_launch": 5}
 PRECS = {"fp32": 0, "bf16": 1, "split_bf16": 2}
@@ -80,6 +82,7 @@ def lib():
         L.smx_simplex_count.argtypes = [_i32, _i64, _i32, _i32, _i32, _vp, _vp, _sz, _vp]
         L.smx_triplet_packed.argtypes = [_vp, _i64, _i64, _dbl, _i32, _vp, _vp, _sz, _vp, _vp]
         L.smx_quad_contacts.argtypes = [_vp, _i64, _i64, _dbl, _i32, _vp, _vp, _sz, _vp, _vp]
+        L.smx_check_flags.argtypes = [ctypes.POINTER(ctypes.c_uint32), _i32]
         L.smx_edm_packed.argtypes = [_vp, _i64, _i64, _i64, _i32, _i32, _vp, _vp, _sz, _vp, _vp]
         L.smx_triplet_energy.argtypes = [_vp, _i64, _i64, ctypes.POINTER(_Pot), _i32, _vp, _vp, _sz, _vp, _vp]
         L.smx_triplet_energy_grad.argtypes = [_vp, _i64, _i64, ctypes.POINTER(_Pot), _i32, _vp, _vp, _vp,
@@ -108,6 +111,22 @@ def _check(rc: int) -> None:
     if rc == 3:
         raise NotImplementedError(msg)
     raise SmxError(msg)
+
+
+def select_library(checked: bool) -> None:
+    """Route every later call through libsmx_checked.so (device checks compiled
+    in) or back through libsmx.so.  Both are built in-tree by build.py."""
+    global LIB_PATH, _lib
+    LIB_PATH = LIB_CHECKED_PATH if checked else os.path.join(_HERE, "libsmx.so")
+    _lib = None
+
+
+def check_flags(clear: bool = True) -> int:
+    """Device check flags of the checked library (bit 1: a map left the simplex,
+    bit 2: a store left it); synchronises with the device."""
+    v = ctypes.c_uint32(0)
+    _check(lib().smx_check_flags(ctypes.byref(v), int(clear)))
+    return int(v.value)
 
 
 def _map(m) -> int:

@@ -461,6 +461,21 @@ int smx_triplet_energy_backward(const float *d_X, int64_t n, int64_t ldx, const 
     return triplet_run(2, d_X, n, ldx, pot, map, nullptr, d_dX, d_gradE, d_ws, ws_bytes, nullptr, stream);
 }
 
+int smx_check_flags(uint32_t *flags, int clear) {
+    if (flags == nullptr) return fail(SMX_EINVAL, "flags must not be NULL");
+    if (!SMX_CHECKED) return fail(SMX_EUNSUPPORTED, "this library is built without device checks");
+    const bool c = clear != 0;
+    const unsigned parts[] = {check_flags_edm(c), check_flags_gram(c), check_flags_map(c),
+                              check_flags_quad(c), check_flags_tripack(c), check_flags_triplet(c)};
+    unsigned v = 0;
+    for (unsigned p : parts) {
+        if (p == ~0u) return fail(SMX_EHIP, "reading the device check flags failed");
+        v |= p;
+    }
+    *flags = v;
+    return SMX_OK;
+}
+
 int smx_quad_contacts(const float *d_X, int64_t n, int64_t ldx, double rc, int map, int64_t *d_count,
                       void *d_ws, size_t ws_bytes, int64_t *d_stats, void *stream) {
     if (n < 0) return fail(SMX_EINVAL, "n must be >= 0");

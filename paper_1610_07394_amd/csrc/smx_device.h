@@ -9,6 +9,30 @@
 namespace smx {
 
 constexpr int kWave = 64;
+
+// Checked builds (compiled with SMX_CHECKED=1 into a separate library): device
+// checks that record a violation in a flag word of the translation unit and
+// skip the access instead of performing it.  Bit kCheckMap: a map produced a
+// tile outside the simplex; bit kCheckStore: a kernel was about to store an
+// element outside the simplex (an unmasked store on a tile it took for
+// interior).  In normal builds the checks compile to nothing.
+#ifndef SMX_CHECKED
+#define SMX_CHECKED 0
+#endif
+constexpr unsigned kCheckMap = 1u, kCheckStore = 2u;
+#if SMX_CHECKED
+static __device__ unsigned int g_check_flags;
+#endif
+__device__ __forceinline__ bool smx_check(bool ok, unsigned bit) {
+#if SMX_CHECKED
+    if (!ok) atomicOr(&g_check_flags, bit);
+    return ok;
+#else
+    (void)ok;
+    (void)bit;
+    return true;
+#endif
+}
 // Statistics and energy partials are accumulated with atomics spread over
 // kSlots addresses, one 128-byte line apart, so that millions of blocks do not
 // serialise on one address.  A finalize kernel sums the slots.
@@ -35,7 +59,7 @@ __device__ __forceinline__ bool launch_tail(const MapGeom &g) {
 // each XCD takes one contiguous range of logical blocks.  The bounding box is
 // the hardware 2-D / 3-D grid itself (identity map, no renumbering).
 template <int MAP, bool XCD>
-__device__ __forceinline__ bool tile2_of(const MapGeom &g, uint64_t &lin, int &X, int &Y) {
+__device__ __forceinline__ bool tile2_raw(const MapGeom &g, uint64_t &lin, int &X, int &Y) {
     if (MAP == MAP_BBOX) {
         X = int(blockIdx.x);
         Y = int(blockIdx.y);
@@ -58,7 +82,7 @@ __device__ __forceinline__ bool tile2_of(const MapGeom &g, uint64_t &lin, int &X
 }
 
 template <int MAP, bool XCD>
-__device__ __forceinline__ bool tile3_of(const MapGeom &g, uint64_t &lin, int &X, int &Y, int &Z) {
+__device__ __forceinline__ bool tile3_raw(const MapGeom &g, uint64_t &lin, int &X, int &Y, int &Z) {
     if (MAP == MAP_BBOX) {
         X = int(blockIdx.x);
         Y = int(blockIdx.y);
@@ -86,7 +110,7 @@ __device__ __forceinline__ bool tile3_of(const MapGeom &g, uint64_t &lin, int &X
 // and the bounding box decodes its block index with divisions by nb.  The
 // from-below map is not defined for m = 4 (the host rejects it).
 template <int MAP, bool XCD>
-__device__ __forceinline__ bool tile4_of(const MapGeom &g, uint64_t &lin, int X[4]) {
+__device__ __forceinline__ bool tile4_raw(const MapGeom &g, uint64_t &lin, int X[4]) {
     lin = uint64_t(blockIdx.y) * gridDim.x + blockIdx.x;
     if (lin >= g.G) return false;
     const uint32_t id = XCD ? xcd_remap(uint32_t(lin), uint32_t(g.G)) : uint32_t(lin);
@@ -112,6 +136,30 @@ __device__ __forceinline__ bool tile4_of(const MapGeom &g, uint64_t &lin, int X[
         return true;
     }
     return false;
+}
+
+// The map entry points used by the kernels: the raw map, then (checked builds)
+// the tile's place in the simplex.
+template <int MAP, bool XCD>
+__device__ __forceinline__ bool tile2_of(const MapGeom &g, uint64_t &lin, int &X, int &Y) {
+    bool ok = tile2_raw<MAP, XCD>(g, lin, X, Y);
+    if (SMX_CHECKED && ok) ok = smx_check(0 <= X && X <= Y && Y < g.nb, kCheckMap);
+    return ok;
+}
+
+template <int MAP, bool XCD>
+__device__ __forceinline__ bool tile3_of(const MapGeom &g, uint64_t &lin, int &X, int &Y, int &Z) {
+    bool ok = tile3_raw<MAP, XCD>(g, lin, X, Y, Z);
+    if (SMX_CHECKED && ok) ok = smx_check(0 <= X && X <= Y && Y <= Z && Z < g.nb, kCheckMap);
+    return ok;
+}
+
+template <int MAP, bool XCD>
+__device__ __forceinline__ bool tile4_of(const MapGeom &g, uint64_t &lin, int X[4]) {
+    bool ok = tile4_raw<MAP, XCD>(g, lin, X);
+    if (SMX_CHECKED && ok)
+        ok = smx_check(0 <= X[0] && X[0] <= X[1] && X[1] <= X[2] && X[2] <= X[3] && X[3] < g.nb, kCheckMap);
+    return ok;
 }
 
 // SplitMix64 finaliser (Steele, Lea, Flood, OOPSLA 2014): the output function

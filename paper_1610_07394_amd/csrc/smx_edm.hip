@@ -121,7 +121,8 @@ __global__ __launch_bounds__(kEdmThreads, 3) void edm_diff_kernel(MapGeom g, con
         for (int c = 0; c < MT; ++c) {
             const int64_t j = c0 + tx + 16 * c;
             // plain stores: measured faster than non-temporal ones here
-            if (interior || (j < n && (!diag || j >= i))) row[16 * c] = acc[r][c];
+            if (interior ? smx_check(i < n && j < n && j >= i, kCheckStore) : (j < n && (!diag || j >= i)))
+                row[16 * c] = acc[r][c];
         }
     }
     if (STATS) {
@@ -166,5 +167,7 @@ int launch_edm_diff(const MapGeom &g, int tile, const float *X, int64_t n, int64
     prof_end(K_EDM_DIFF, s);
     return check_launch("edm_packed (fp32 diff)");
 }
+
+SMX_CHECK_READER(check_flags_edm)
 
 }  // namespace smx

@@ -282,7 +282,8 @@ __global__ __launch_bounds__(kGramThreads) void edm_gram_kernel(MapGeom g, const
             const float4 v = *reinterpret_cast<const float4 *>(St + rl * WT + cl);
             float *dst = D + (i * n - (i * (i - 1)) / 2 - i) + j;
             if (interior) {
-                *reinterpret_cast<float4 *>(dst) = v;  // 4-byte aligned: the packed rows start anywhere
+                if (smx_check(i < n && j >= i && j + 3 < n, kCheckStore))
+                    *reinterpret_cast<float4 *>(dst) = v;  // 4-byte aligned: the packed rows start anywhere
             } else if (i < n) {
                 const float vv[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
@@ -326,5 +327,7 @@ int launch_edm_gram(const MapGeom &g, int tile, const uint16_t *hi, const uint16
     prof_end(K_EDM_GRAM, s);
     return check_launch("edm_packed (gram)");
 }
+
+SMX_CHECK_READER(check_flags_gram)
 
 }  // namespace smx

@@ -15,6 +15,30 @@ int fail(int code, const char *fmt, ...);
 // Map a HIP error (if any) to SMX_EHIP with a message.
 int check_launch(const char *what);
 
+// Checked builds: each kernel translation unit has its own device flag word;
+// these read it (and clear it when asked).  ~0u if the copy failed.
+#if SMX_CHECKED
+#define SMX_CHECK_READER(name)                                                                   \
+    unsigned name(bool clear) {                                                                  \
+        unsigned v = 0;                                                                          \
+        if (hipMemcpyFromSymbol(&v, HIP_SYMBOL(g_check_flags), sizeof(v)) != hipSuccess) return ~0u; \
+        if (clear) {                                                                             \
+            const unsigned z = 0;                                                                \
+            if (hipMemcpyToSymbol(HIP_SYMBOL(g_check_flags), &z, sizeof(z)) != hipSuccess) return ~0u; \
+        }                                                                                        \
+        return v;                                                                                \
+    }
+#else
+#define SMX_CHECK_READER(name) \
+    unsigned name(bool) { return 0; }
+#endif
+unsigned check_flags_edm(bool clear);
+unsigned check_flags_gram(bool clear);
+unsigned check_flags_map(bool clear);
+unsigned check_flags_quad(bool clear);
+unsigned check_flags_tripack(bool clear);
+unsigned check_flags_triplet(bool clear);
+
 // Kernel ids for the timing facility (match smx_profile_read).
 enum KernelId {
     K_MAP2 = 0, K_MAP3 = 1, K_EDM_DIFF = 2, K_EDM_GRAM = 3, K_GRAM_PREP = 4,

@@ -313,4 +313,6 @@ int launch_map3(const MapGeom &g, int64_t n, int rho, int map, int strict, int32
     return check_launch("simplex_map3");
 }
 
+SMX_CHECK_READER(check_flags_map)
+
 }  // namespace smx

@@ -183,4 +183,6 @@ int launch_count_finalize(const unsigned long long *slots, int64_t *out, hipStre
     return check_launch("count finalize");
 }
 
+SMX_CHECK_READER(check_flags_quad)
+
 }  // namespace smx

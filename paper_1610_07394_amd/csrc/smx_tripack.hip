@@ -111,7 +111,7 @@ __global__ __launch_bounds__(kPackThreads) void at_packed_kernel(MapGeom g, cons
             // (a.b)(b.c)(c.a) with c = -(x_k - x_i): the two sign flips cancel
             const float inner = __builtin_fmaf(-3.f, (ab * bc) * (ca * R2), 1.f);
             const float e = inner * (nu * (R2 * R));
-            const bool ok = interior || (i < j && j < k && k < n);
+            const bool ok = interior ? smx_check(i < j && j < k && k < n, kCheckStore) : (i < j && j < k && k < n);
             if (ok) out[rowj - jl] = e;
             if (STATS && ok) {
                 ++cnt;
@@ -146,5 +146,7 @@ int launch_triplet_packed(const MapGeom &g, const float *X, int64_t n, int64_t l
     prof_end(K_TRIP_PACKED, s);
     return check_launch("triplet packed");
 }
+
+SMX_CHECK_READER(check_flags_tripack)
 
 }  // namespace smx

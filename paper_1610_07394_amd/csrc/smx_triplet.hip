@@ -543,4 +543,6 @@ int launch_grad_finalize(const double *G64, int64_t n, const double *gradE, floa
     return check_launch("grad finalize");
 }
 
+SMX_CHECK_READER(check_flags_triplet)
+
 }  // namespace smx
