@@ -38,7 +38,10 @@ LJ_FLOPS = 30                              # declared flops per pair (fwd + bwd)
 # rocprofv3 PMC passes (FETCH_SIZE, WRITE_SIZE, scaled by a 1 GiB copy) recorded
 # in profiles/step_lambda_hbm_traffic_pmc.md.  They describe the kernel built
 # from sources with this hash; once those change the figure is reported as null.
-AT_TRAFFIC = {"src_sha16": "ec04e7f17bdac2a6", "fetch_bytes": 0.000934e9, "write_bytes": 19.645e9}
+AT_TRAFFIC = {"src_sha16": "ec04e7f17bdac2a6", "fetch_bytes": 0.000934e9, "write_bytes": 19.645e9,
+              "valu_instructions": 42596757504}  # SQ_INSTS_VALU (wave instructions) per launch
+# single-issue FP32 vector rate: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
+VALU_ISSUE_SPEC = 256 * 4 * 16 * 2.4e9
 AT_SOURCES = ("smx_triplet.hip", "smx_device.h", "smx_maps.h")
 
 N_EDM, D_EDM = 65536, 64
@@ -282,6 +285,12 @@ def main():
                 "traffic_fetch_bytes": None if traffic is None else traffic[0],
                 "traffic_write_bytes": None if traffic is None else traffic[1],
                 "per_unit": "80 flops per triplet (20 forward + 60 backward), 9.159e10 triplets per launch"}
+        if traffic is not None:
+            issue = traffic[2] * 64 / t  # VALU lane-instructions per second
+            ceil = valu_ceiling(smx, torch, dev)
+            roof["valu_issue"] = {"lane_instructions_per_s": issue, "per_triplet": traffic[2] * 64 / math.comb(N_AT, 3),
+                                  "spec_single_issue": VALU_ISSUE_SPEC, "frac_spec": issue / VALU_ISSUE_SPEC,
+                                  "measured_fma_chain": ceil, "frac_measured": issue / ceil}
     elif dom == "edm_diff":
         t = kavg[dom] / 1e3
         ach = 3 * D_EDM * elements["edm"] / t
@@ -384,7 +393,24 @@ def at_traffic():
             h.update(fh.read())
     if h.hexdigest()[:16] != AT_TRAFFIC["src_sha16"]:
         return None
-    return AT_TRAFFIC["fetch_bytes"], AT_TRAFFIC["write_bytes"]
+    return AT_TRAFFIC["fetch_bytes"], AT_TRAFFIC["write_bytes"], AT_TRAFFIC["valu_instructions"]
+
+
+def valu_ceiling(smx, torch, dev):
+    """Measured FP32 VALU issue rate (lane operations / s): the library's FMA-chain
+    probe, best of three launches timed with events on the current stream."""
+    blocks, iters = 8192, 2048
+    out = torch.empty(blocks * 256, dtype=torch.float32, device=dev)
+    best = None
+    for _ in range(4):
+        ev = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev[0].record()
+        smx._check(smx.lib().smx_probe_valu(out.data_ptr(), blocks, iters, smx._stream()))
+        ev[1].record()
+        torch.cuda.synchronize()
+        ms = ev[0].elapsed_time(ev[1])
+        best = ms if best is None else min(best, ms)
+    return blocks * 256 * iters * 64 / (best / 1e3)
 
 
 def cpu_baseline(only, elements, total_elems):

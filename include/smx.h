@@ -286,6 +286,14 @@ int smx_triplet_packed(const float *d_X, int64_t n, int64_t ldx, double nu, int 
 int smx_quad_contacts(const float *d_X, int64_t n, int64_t ldx, double rc, int map, int64_t *d_count,
                       void *d_ws, size_t ws_bytes, int64_t *d_stats, void *stream);
 
+/* Measurement probe for the roofline of the VALU-bound kernels (not part of
+ * the simplex path): enqueues `blocks` blocks of 256 threads, each thread
+ * running iters x 64 FP32 fused multiply-adds in eight independent chains with
+ * no memory traffic, then one store to d_out[blocks * 256] (FP32, device,
+ * caller-owned).  The caller times it on `stream`; lane operations =
+ * blocks * 256 * iters * 64.  blocks in [1, 2^24], iters >= 1. */
+int smx_probe_valu(float *d_out, int64_t blocks, int iters, void *stream);
+
 /* Device checks.  The library can be built a second time with SMX_CHECKED=1
  * (libsmx_checked.so, same ABI): every map evaluation then verifies that its
  * tile lies in the simplex, and every unmasked store on a tile taken for

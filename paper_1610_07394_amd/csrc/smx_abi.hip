@@ -461,6 +461,13 @@ int smx_triplet_energy_backward(const float *d_X, int64_t n, int64_t ldx, const 
     return triplet_run(2, d_X, n, ldx, pot, map, nullptr, d_dX, d_gradE, d_ws, ws_bytes, nullptr, stream);
 }
 
+int smx_probe_valu(float *d_out, int64_t blocks, int iters, void *stream) {
+    if (d_out == nullptr) return fail(SMX_EINVAL, "out must not be NULL");
+    if (blocks < 1 || blocks > (int64_t(1) << 24)) return fail(SMX_EINVAL, "blocks must be in [1, 2^24]");
+    if (iters < 1) return fail(SMX_EINVAL, "iters must be >= 1");
+    return launch_valu_probe(d_out, blocks, iters, S(stream));
+}
+
 int smx_check_flags(uint32_t *flags, int clear) {
     if (flags == nullptr) return fail(SMX_EINVAL, "flags must not be NULL");
     if (!SMX_CHECKED) return fail(SMX_EUNSUPPORTED, "this library is built without device checks");

@@ -160,6 +160,7 @@ int launch_contact_words(const MapGeom &g, const float *X, int64_t n, int64_t ld
 int launch_quad(const MapGeom &g, const uint64_t *W, int64_t npad, int64_t n, unsigned long long *cslots,
                 unsigned long long *sslots, hipStream_t s);
 int launch_count_finalize(const unsigned long long *slots, int64_t *out, hipStream_t s);
+int launch_valu_probe(float *out, int64_t blocks, int iters, hipStream_t s);
 int launch_grad_finalize(const double *G64, int64_t n, const double *gradE, float *out,
                          hipStream_t s);
 int launch_scale_grad(const float *G, int64_t n, const double *gradE, float *out, hipStream_t s);
