@@ -215,6 +215,7 @@ def main():
     # packed per-triplet energies, n = 2048 (the write-bound 3-simplex workload;
     # measured beside the step, not part of it)
     if "at" in only and not args.no_compare:
+        log("packed triplet energies, n = 2048")
         Xp = torch.from_numpy(synth.workload_input("at_n2048")).to(dev)
         npk = Xp.shape[0]
         mpk = npk * (npk - 1) * (npk - 2) // 6
@@ -248,6 +249,7 @@ def main():
     # 4-point contacts over the 4-simplex, n = 8192 (measured beside the step):
     # contact words over the 2-simplex, then the 4-cliques per 64^4 tile
     if "at" in only and not args.no_compare:
+        log("4-point contacts, n = 8192")
         qd = {}
         ws4 = torch.empty(smx.workspace_bytes(3, N_AT), dtype=torch.uint8, device=dev)
         cnt = torch.empty(1, dtype=torch.int64, device=dev)
@@ -308,6 +310,7 @@ def main():
     compare = None
     if not args.no_compare:
         compare = {}
+        log("step on the other maps")
         for kind in (QUICK_MAPS if args.quick_compare else ALL_MAPS)[1:]:
             step(kind)  # warm
             torch.cuda.synchronize()
@@ -330,6 +333,7 @@ def main():
         # checksum); "count" = each mapped block adds its tile's closed-form
         # count, so the time is the map plus the launched blocks alone.
         mo = {}
+        log("map-only parallel spaces")
         for kind in () if args.quick_compare else ("lambda", "bbox", "linear", "lambda_below", "recursive", "recursive_launch"):
             for m, n, rho in ((2, N_EDM, 16), (3, N_AT, 8), (4, N_MAP4, 8)):
                 if m == 4 and kind == "lambda_below":
@@ -352,6 +356,7 @@ def main():
     # ---- CPU baseline: the FP64 oracle on a bounded sample, host cores
     cpu = None
     if not args.no_cpu_baseline:
+        log("CPU baseline (oracle)")
         cpu = cpu_baseline(only, elements, total_elems)
 
     out = {
