@@ -136,6 +136,16 @@ int64_t smx_parallel_blocks(int m, int64_t n, int rho, int map);
 int smx_map_tiles_host(int m, int64_t n, int rho, int map, int64_t first, int64_t count,
                        int32_t *tiles);
 
+/* Inverse maps: for each of `count` tiles (host int32[count][m], each in the
+ * target simplex T2 / T3 of nb = ceil(n / rho) tiles), the index of the block
+ * that `map` sends to it, written to host ids[count].  A tile X < Y of lambda2
+ * lies on the level b = 2^L of the recursion with L = msb(X xor Y) and in its
+ * square X >> (L+1) (Sec. III-A); a tile X <= Y < Z of lambda3 on the level of
+ * msb(X xor Z) (the Sec. III-C reading).  Maps: LAMBDA, BBOX, LINEAR for m = 2
+ * and 3 (SMX_EUNSUPPORTED otherwise); SMX_EINVAL for a tile outside the
+ * simplex.  Host only. */
+int smx_map_blocks_host(int m, int64_t n, int rho, int map, const int32_t *tiles, int64_t count, int64_t *ids);
+
 /* Workspace bytes the calls below need (0 if none).  `op`: 0 = simplex_map
  * (any m), 1 = edm_packed, 2 = triplet calls, 3 = quad_contacts.  Host only;
  * 0 also on bad arguments. */

@@ -15,7 +15,7 @@ from dataclasses import dataclass
 import torch
 
 __all__ = [
-    "MAPS", "PRECS", "SmxError", "Pot", "lib", "volume", "parallel_blocks", "map_tiles_host",
+    "MAPS", "PRECS", "SmxError", "Pot", "lib", "volume", "parallel_blocks", "map_tiles_host", "map_blocks_host",
     "workspace_bytes", "simplex_map2", "simplex_map3", "simplex_map4", "simplex_count", "triplet_packed", "quad_contacts", "edm_packed", "triplet_energy",
     "triplet_energy_grad", "triplet_energy_backward", "TripletEnergy", "profile_enable",
     "profile_reset", "profile_read", "KERNELS", "select_library", "check_flags",
@@ -83,6 +83,7 @@ def lib():
         L.smx_triplet_packed.argtypes = [_vp, _i64, _i64, _dbl, _i32, _vp, _vp, _sz, _vp, _vp]
         L.smx_quad_contacts.argtypes = [_vp, _i64, _i64, _dbl, _i32, _vp, _vp, _sz, _vp, _vp]
         L.smx_check_flags.argtypes = [ctypes.POINTER(ctypes.c_uint32), _i32]
+        L.smx_map_blocks_host.argtypes = [_i32, _i64, _i32, _i32, _vp, _i64, _vp]
         L.smx_probe_valu.argtypes = [_vp, _i64, _i32, _vp]
         L.smx_edm_packed.argtypes = [_vp, _i64, _i64, _i64, _i32, _i32, _vp, _vp, _sz, _vp, _vp]
         L.smx_triplet_energy.argtypes = [_vp, _i64, _i64, ctypes.POINTER(_Pot), _i32, _vp, _vp, _sz, _vp, _vp]
@@ -167,6 +168,15 @@ def map_tiles_host(m: int, n: int, rho: int, map="lambda", first: int = 0, count
         count = parallel_blocks(m, n, rho, map) - first
     out = np.empty((count, m), dtype=np.int32)
     _check(lib().smx_map_tiles_host(m, n, rho, _map(map), first, count, out.ctypes.data))
+    return out
+
+
+def map_blocks_host(m: int, n: int, rho: int, tiles, map="lambda"):
+    """Block index of each tile (numpy int32 [count, m]) under `map` (the inverse map), on the host."""
+    import numpy as np
+    t = np.ascontiguousarray(tiles, dtype=np.int32).reshape(-1, m)
+    out = np.empty(t.shape[0], dtype=np.int64)
+    _check(lib().smx_map_blocks_host(m, n, rho, _map(map), t.ctypes.data, t.shape[0], out.ctypes.data))
     return out
 
 

@@ -11,6 +11,7 @@
 
 #include "smx_device.h"
 #include "smx_internal.h"
+#include "smx_maps_inv.h"
 
 namespace smx {
 
@@ -299,6 +300,32 @@ int smx_map_tiles_host(int m, int64_t n, int rho, int map, int64_t first, int64_
             o[1] = ok ? Y : -1;
             o[2] = ok ? Z : -1;
         }
+    }
+    return SMX_OK;
+}
+
+int smx_map_blocks_host(int m, int64_t n, int rho, int map, const int32_t *tiles, int64_t count, int64_t *ids) {
+    int rc = check_common(m, n, rho, map, max_rho(m));
+    if (rc != SMX_OK) return rc;
+    if (m == 4 || (map != MAP_LAMBDA && map != MAP_BBOX && map != MAP_LINEAR))
+        return fail(SMX_EUNSUPPORTED, "inverse maps exist for lambda, bounding box and linear with m = 2, 3");
+    if (count < 0) return fail(SMX_EINVAL, "negative count");
+    if (count == 0) return SMX_OK;
+    if (tiles == nullptr || ids == nullptr) return fail(SMX_EINVAL, "tiles and ids must not be NULL");
+    if (n == 0) return fail(SMX_EINVAL, "n = 0 has no tiles");
+    MapGeom g;
+    if (!make_geom(m, (n + rho - 1) / rho, map, g)) return g_status;
+    for (int64_t e = 0; e < count; ++e) {
+        const int32_t *t = tiles + e * m;
+        bool in = true;
+        for (int d = 0; d < m; ++d) in = in && t[d] >= 0 && t[d] < g.nb && (d == 0 || t[d - 1] <= t[d]);
+        if (!in) return fail(SMX_EINVAL, "tile %lld is not in the simplex", (long long)e);
+        const uint32_t X = uint32_t(t[0]), Y = uint32_t(t[1]), Z = m == 3 ? uint32_t(t[2]) : 0;
+        uint64_t id;
+        if (map == MAP_LAMBDA) id = m == 2 ? lambda2_inv(g.lg, X, Y) : lambda3_inv(g.lg, g.main, X, Y, Z);
+        else if (map == MAP_BBOX) id = m == 2 ? uint64_t(Y) * g.nb + X : (uint64_t(Z) * g.nb + Y) * g.nb + X;
+        else id = m == 2 ? linear2_inv(X, Y) : linear3_inv(X, Y, Z);
+        ids[e] = int64_t(id);
     }
     return SMX_OK;
 }

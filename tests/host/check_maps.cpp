@@ -1,13 +1,14 @@
 // Host build of the library's block-space maps (the same inline header the
 // kernels use), for running under AddressSanitizer and UndefinedBehaviorSanitizer:
 // every block of every map is decoded for a range of nb, and the mapped tiles
-// must cover the target simplex exactly once, with no shift, overflow or
-// out-of-range access along the way.  Exit status 0 and "ok" on success.
+// must cover the target simplex exactly once (and the lambda inverses must
+// return each block), with no shift, overflow or out-of-range access.  Exit status 0 and "ok" on success.
 #include <cstdio>
 #include <cstdlib>
 #include <vector>
 
 #include "smx_maps.h"
+#include "smx_maps_inv.h"
 
 using namespace smx;
 
@@ -73,6 +74,13 @@ static void check(int m, int nb, int map) {
             }
         }
         if (!ok) continue;
+        if (map == MAP_LAMBDA && m <= 3) {  // the inverse map returns this block
+            const uint64_t back = m == 2 ? lambda2_inv(lg, uint32_t(t[0]), uint32_t(t[1]))
+                                         : lambda3_inv(lg, main, uint32_t(t[0]), uint32_t(t[1]), uint32_t(t[2]));
+            if (back != id && fails++ < 10)
+                std::printf("m=%d nb=%d: inverse of block %llu gave %llu\n", m, nb, (unsigned long long)id,
+                            (unsigned long long)back);
+        }
         const long long r = rank_tuple(t, m);
         if (seen[size_t(r)]++) {
             if (fails++ < 10) std::printf("m=%d nb=%d map=%d: tile mapped twice\n", m, nb, map);

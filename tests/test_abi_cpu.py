@@ -209,3 +209,27 @@ def test_binding_rejects_host_tensors():
         smx.edm_packed(X)
     with pytest.raises(ValueError):
         smx.triplet_energy(X)
+
+
+@pytest.mark.parametrize("m,nbs", [(2, [1, 2, 3, 4, 7, 8, 16, 33, 64, 100, 512]), (3, [1, 2, 3, 4, 5, 8, 16, 31, 64])])
+@pytest.mark.parametrize("kind", ["lambda", "bbox", "linear"])
+def test_inverse_maps_round_trip(m, nbs, kind):
+    """The library's inverse maps send every mapped tile back to the block that
+    mapped it, and every tile of the simplex to a block that maps to it."""
+    for nb in nbs:
+        t = smx.map_tiles_host(m, nb, 1, kind)
+        ok = t[:, 0] >= 0
+        ids = smx.map_blocks_host(m, nb, 1, t[ok], kind)
+        np.testing.assert_array_equal(ids, np.nonzero(ok)[0])
+        target = np.array(sorted(omaps.target_tiles(m, nb)), dtype=np.int32)
+        back = smx.map_tiles_host(m, nb, 1, kind)[smx.map_blocks_host(m, nb, 1, target, kind)]
+        np.testing.assert_array_equal(back, target)
+
+
+def test_inverse_maps_reject_bad_tiles():
+    with pytest.raises(ValueError):
+        smx.map_blocks_host(2, 8, 1, [[3, 2]])
+    with pytest.raises(ValueError):
+        smx.map_blocks_host(3, 8, 1, [[0, 1, 8]])
+    with pytest.raises(NotImplementedError):
+        smx.map_blocks_host(2, 8, 1, [[0, 1]], "recursive")
