@@ -271,6 +271,17 @@ int smx_triplet_energy_backward(const float *d_X, int64_t n, int64_t ldx, const 
 int smx_triplet_packed(const float *d_X, int64_t n, int64_t ldx, double nu, int map, float *d_E, void *d_ws,
                        size_t ws_bytes, int64_t *d_stats, void *stream);
 
+/* The same per-triplet energies in a tile-contiguous layout, so that each
+ * 32^3 tile is written as one contiguous 128 KB run.  With nb = ceil(n / 32),
+ * d_E holds C(nb+2, 3) * 32768 floats: tile (X, Y, Z), X <= Y <= Z < nb, starts
+ * at rank * 32768 with rank = Z(Z+1)(Z+2)/6 + Y(Y+1)/2 + X, and triplet (i, j, k)
+ * sits at offset 1024 (i mod 32) + 32 (j mod 32) + (k mod 32) of tile
+ * (i/32, j/32, k/32); the entries of a tile that are not triplets i < j < k < n
+ * are 0.  The values are those of smx_triplet_packed, bit for bit.  Arguments,
+ * limits and errors as smx_triplet_packed. */
+int smx_triplet_packed_tiled(const float *d_X, int64_t n, int64_t ldx, double nu, int map, float *d_E,
+                             void *d_ws, size_t ws_bytes, int64_t *d_stats, void *stream);
+
 /* 4-point contacts on the 4-simplex (Sec. I: correlation counts over the
  * simplex; Sec. III-D: the 4-simplex parallel space).  Counts the quadruplets
  * i < j < k < l whose six pairs are all in contact -- the 4-cliques of the
@@ -326,7 +337,7 @@ int smx_scale_grad(const float *d_G, int64_t n, const double *d_gradE, float *d_
  * returns the summed duration (ms) and launch count of kernel `kernel_id`
  * (0 map2, 1 map3, 2 edm diff, 3 edm gram, 4 gram prep, 5 triplet energy,
  * 6 triplet grad, 7 lj, 8 finalize, 9 triplet packed, 10 map4, 11 contact words,
- * 12 quad contacts) since the last reset; it
+ * 12 quad contacts, 13 triplet packed tiled) since the last reset; it
  * returns SMX_EINVAL
  * for an unknown id.  smx_profile_reset clears the totals.  Host only. */
 int smx_profile_enable(int on);

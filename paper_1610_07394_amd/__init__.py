@@ -16,7 +16,7 @@ import torch
 
 __all__ = [
     "MAPS", "PRECS", "SmxError", "Pot", "lib", "volume", "parallel_blocks", "map_tiles_host", "map_blocks_host",
-    "workspace_bytes", "simplex_map2", "simplex_map3", "simplex_map4", "simplex_count", "triplet_packed", "quad_contacts", "edm_packed", "triplet_energy",
+    "workspace_bytes", "simplex_map2", "simplex_map3", "simplex_map4", "simplex_count", "triplet_packed", "triplet_packed_tiled", "triplet_tiled_len", "quad_contacts", "edm_packed", "triplet_energy",
     "triplet_energy_grad", "triplet_energy_backward", "TripletEnergy", "profile_enable",
     "profile_reset", "profile_read", "KERNELS", "select_library", "check_flags",
 ]
@@ -30,7 +30,7 @@ MAPS = {"lambda": 0, "bbox": 1, "linear": 2, "lambda_below": 3, "recursive": 4, 
 PRECS = {"fp32": 0, "bf16": 1, "split_bf16": 2}
 KERNELS = {"map2": 0, "map3": 1, "edm_diff": 2, "edm_gram": 3, "gram_prep": 4,
            "triplet_energy": 5, "triplet_grad": 6, "lj": 7, "finalize": 8, "triplet_packed": 9, "map4": 10,
-           "quad_words": 11, "quad": 12}
+           "quad_words": 11, "quad": 12, "triplet_tiled": 13}
 
 _i32, _i64, _sz, _vp, _dbl = ctypes.c_int, ctypes.c_int64, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_double
 
@@ -81,6 +81,7 @@ def lib():
             getattr(L, name).argtypes = [_i64, _i32, _i32, _i32, _vp, _vp, _vp, _sz, _vp]
         L.smx_simplex_count.argtypes = [_i32, _i64, _i32, _i32, _i32, _vp, _vp, _sz, _vp]
         L.smx_triplet_packed.argtypes = [_vp, _i64, _i64, _dbl, _i32, _vp, _vp, _sz, _vp, _vp]
+        L.smx_triplet_packed_tiled.argtypes = [_vp, _i64, _i64, _dbl, _i32, _vp, _vp, _sz, _vp, _vp]
         L.smx_quad_contacts.argtypes = [_vp, _i64, _i64, _dbl, _i32, _vp, _vp, _sz, _vp, _vp]
         L.smx_check_flags.argtypes = [ctypes.POINTER(ctypes.c_uint32), _i32]
         L.smx_map_blocks_host.argtypes = [_i32, _i64, _i32, _i32, _vp, _i64, _vp]
@@ -278,6 +279,29 @@ def triplet_packed(X: torch.Tensor, nu: float = 1.0, map="lambda", stats=False, 
         ws = _ws(workspace_bytes(0, n), X.device)
     _check(lib().smx_triplet_packed(xp, n, ldx, float(nu), _map(map), _ptr(E), _ptr(ws),
                                     0 if ws is None else ws.numel(), _ptr(s), _stream()))
+    return (E, s) if stats else E
+
+
+def triplet_tiled_len(n: int) -> int:
+    """Floats of the tile-contiguous per-triplet layout: C(nb+2, 3) tiles of 32^3."""
+    nb = -(-n // 32)
+    return nb * (nb + 1) * (nb + 2) // 6 * 32768
+
+
+def triplet_packed_tiled(X: torch.Tensor, nu: float = 1.0, map="lambda", stats=False, out=None, ws=None):
+    """Per-triplet Axilrod-Teller energies in the tile-contiguous layout (FP32
+    [C(nb+2,3) * 32768], see smx_triplet_packed_tiled); with stats=True also the
+    int64 [4] counters."""
+    xp, n, ldx = _xarg(X)
+    m = triplet_tiled_len(n) if n >= 3 else 0
+    E = out if out is not None else torch.empty(m, dtype=torch.float32, device=X.device)
+    if E.dtype != torch.float32 or E.numel() < m or not E.is_contiguous() or E.device != X.device:
+        raise ValueError("out must be a contiguous FP32 tensor of triplet_tiled_len(n) elements on X's device")
+    s = torch.zeros(4, dtype=torch.int64, device=X.device) if stats else None
+    if stats and ws is None:
+        ws = _ws(workspace_bytes(0, n), X.device)
+    _check(lib().smx_triplet_packed_tiled(xp, n, ldx, float(nu), _map(map), _ptr(E), _ptr(ws),
+                                          0 if ws is None else ws.numel(), _ptr(s), _stream()))
     return (E, s) if stats else E
 
 

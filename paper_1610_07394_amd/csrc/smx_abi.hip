@@ -541,8 +541,8 @@ int smx_quad_contacts(const float *d_X, int64_t n, int64_t ldx, double rc, int m
     return SMX_OK;
 }
 
-int smx_triplet_packed(const float *d_X, int64_t n, int64_t ldx, double nu, int map, float *d_E, void *d_ws,
-                       size_t ws_bytes, int64_t *d_stats, void *stream) {
+static int triplet_packed_run(bool tiled, const float *d_X, int64_t n, int64_t ldx, double nu, int map, float *d_E,
+                              void *d_ws, size_t ws_bytes, int64_t *d_stats, void *stream) {
     if (n < 0) return fail(SMX_EINVAL, "n must be >= 0");
     if (n > (int64_t(1) << 21)) return fail(SMX_EOVERFLOW, "n = %lld exceeds 2^21 (C(n,3) must fit 63 bits)", (long long)n);
     if (ldx < 3) return fail(SMX_EINVAL, "ldx (%lld) < 3", (long long)ldx);
@@ -555,9 +555,19 @@ int smx_triplet_packed(const float *d_X, int64_t n, int64_t ldx, double nu, int 
     unsigned long long *slots = d_stats ? reinterpret_cast<unsigned long long *>(d_ws) : nullptr;
     int rc;
     if (slots && (rc = launch_fill_u64(reinterpret_cast<uint64_t *>(slots), kSlotBytes / 8, S(stream)))) return rc;
-    if (n >= 3 && (rc = launch_triplet_packed(g, d_X, n, ldx, float(nu), d_E, slots, S(stream)))) return rc;
+    if (n >= 3 && (rc = launch_triplet_packed(g, d_X, n, ldx, float(nu), d_E, slots, tiled, S(stream)))) return rc;
     if (slots) return launch_stats_finalize(slots, g.G, d_stats, S(stream));
     return SMX_OK;
+}
+
+int smx_triplet_packed(const float *d_X, int64_t n, int64_t ldx, double nu, int map, float *d_E, void *d_ws,
+                       size_t ws_bytes, int64_t *d_stats, void *stream) {
+    return triplet_packed_run(false, d_X, n, ldx, nu, map, d_E, d_ws, ws_bytes, d_stats, stream);
+}
+
+int smx_triplet_packed_tiled(const float *d_X, int64_t n, int64_t ldx, double nu, int map, float *d_E, void *d_ws,
+                             size_t ws_bytes, int64_t *d_stats, void *stream) {
+    return triplet_packed_run(true, d_X, n, ldx, nu, map, d_E, d_ws, ws_bytes, d_stats, stream);
 }
 
 int smx_scale_grad(const float *d_G, int64_t n, const double *d_gradE, float *d_out, void *stream) {

@@ -43,7 +43,7 @@ unsigned check_flags_triplet(bool clear);
 enum KernelId {
     K_MAP2 = 0, K_MAP3 = 1, K_EDM_DIFF = 2, K_EDM_GRAM = 3, K_GRAM_PREP = 4,
     K_TRIP_ENERGY = 5, K_TRIP_GRAD = 6, K_LJ = 7, K_FINALIZE = 8, K_TRIP_PACKED = 9, K_MAP4 = 10,
-    K_QUAD_WORDS = 11, K_QUAD = 12, K_COUNT = 13
+    K_QUAD_WORDS = 11, K_QUAD = 12, K_TRIP_TILED = 13, K_COUNT = 14
 };
 void prof_begin(int kid, hipStream_t s);
 void prof_end(int kid, hipStream_t s);
@@ -153,7 +153,7 @@ int launch_lj(const MapGeom &g, const float *X, int64_t n, int64_t ldx, float ep
               float rc2, double *G64, double *eslots, unsigned long long *sslots, hipStream_t s);
 int launch_energy_finalize(const double *eslots, double *E, hipStream_t s);
 int launch_triplet_packed(const MapGeom &g, const float *X, int64_t n, int64_t ldx, float nu, float *E,
-                          unsigned long long *sslots, hipStream_t s);
+                          unsigned long long *sslots, bool tiled, hipStream_t s);
 constexpr int kQuadTile = 64;    // 4-point contacts: 64 elements per tile dimension
 int launch_contact_words(const MapGeom &g, const float *X, int64_t n, int64_t ldx, float rc2, uint64_t *W,
                          int64_t npad, hipStream_t s);

@@ -17,6 +17,7 @@
 // 4-byte store: the kernel is bound by the stores.
 //
 // Block: 256 threads own the 32^3 triplets of tile (X, Y, Z), X <= Y <= Z.
+// (A second, tile-contiguous output layout is described at the kernel.)
 //   1. positions of the three tiles -> LDS;
 //   2. per pair of the sets (i,j), (i,k), (j,k) the difference vector and
 //      d = 1/r -> LDS as one float4, stored [i][j], [i][k], [j][k]; d = 0 for a
@@ -32,7 +33,13 @@ namespace smx {
 
 constexpr int kPackThreads = 256;
 
-template <int MAP, bool STATS>
+// TILED: the tile-contiguous layout instead of the lexicographic one.  Tile
+// (X, Y, Z) of T3 owns the 32^3 floats starting at rank(X, Y, Z) * 32^3, rank =
+// Z(Z+1)(Z+2)/6 + Y(Y+1)/2 + X (the tile's place in the listing by Z, Y, X);
+// element (i, j, k) sits at offset 1024 (i mod 32) + 32 (j mod 32) + (k mod 32)
+// inside it, and the tile's entries that are not triplets i < j < k < n hold
+// 0.  Every tile is then one contiguous 128 KB run, written in full.
+template <int MAP, bool STATS, bool TILED>
 __global__ __launch_bounds__(kPackThreads) void at_packed_kernel(MapGeom g, const float *__restrict__ Xp,
                                                                  int64_t n, int64_t ldx, float nu,
                                                                  float *__restrict__ E,
@@ -98,6 +105,11 @@ __global__ __launch_bounds__(kPackThreads) void at_packed_kernel(MapGeom g, cons
         int64_t rowj = c3 - ni * (ni - 1) * (ni - 2) / 6 + (j0 - i - 1) * (n - 1) - (j0 * (j0 - 1) / 2 - i * (i + 1) / 2) -
                        j0 - 1;
         float *out = E + k;
+        if (TILED) {
+            const uint64_t Z = uint64_t(TZ), Y = uint64_t(TY);
+            const uint64_t rank = Z * (Z + 1) * (Z + 2) / 6 + Y * (Y + 1) / 2 + uint64_t(TX);
+            out = E + rank * uint64_t(T * T * T) + uint64_t(il * T * T + kl);
+        }
 #pragma unroll 4
         for (int jl = 0; jl < T; ++jl) {
             const int64_t j = j0 + jl;
@@ -111,8 +123,12 @@ __global__ __launch_bounds__(kPackThreads) void at_packed_kernel(MapGeom g, cons
             // (a.b)(b.c)(c.a) with c = -(x_k - x_i): the two sign flips cancel
             const float inner = __builtin_fmaf(-3.f, (ab * bc) * (ca * R2), 1.f);
             const float e = inner * (nu * (R2 * R));
-            const bool ok = interior ? smx_check(i < j && j < k && k < n, kCheckStore) : (i < j && j < k && k < n);
-            if (ok) out[rowj - jl] = e;
+            const bool ok = TILED ? (i < j && j < k && k < n)
+                          : interior ? smx_check(i < j && j < k && k < n, kCheckStore) : (i < j && j < k && k < n);
+            if (TILED)
+                out[jl * T] = ok ? e : 0.f;
+            else if (ok)
+                out[rowj - jl] = e;
             if (STATS && ok) {
                 ++cnt;
                 cs += mix64(id_trip_lt(uint64_t(i), uint64_t(j), uint64_t(k)));
@@ -127,23 +143,28 @@ __global__ __launch_bounds__(kPackThreads) void at_packed_kernel(MapGeom g, cons
     }
 }
 
-template <int MAP>
+template <int MAP, bool TILED>
 static void go_packed(const MapGeom &g, const float *X, int64_t n, int64_t ldx, float nu, float *E,
                       unsigned long long *sslots, hipStream_t s) {
     const dim3 grid = MAP == MAP_BBOX ? dim3(g.nb, g.nb, g.nb) : grid_for(g.G, kPackThreads);
     if (sslots)
-        hipLaunchKernelGGL((at_packed_kernel<MAP, true>), grid, dim3(kPackThreads), 0, s, g, X, n, ldx, nu, E,
-                           sslots);
+        hipLaunchKernelGGL((at_packed_kernel<MAP, true, TILED>), grid, dim3(kPackThreads), 0, s, g, X, n, ldx, nu,
+                           E, sslots);
     else
-        hipLaunchKernelGGL((at_packed_kernel<MAP, false>), grid, dim3(kPackThreads), 0, s, g, X, n, ldx, nu, E,
-                           sslots);
+        hipLaunchKernelGGL((at_packed_kernel<MAP, false, TILED>), grid, dim3(kPackThreads), 0, s, g, X, n, ldx, nu,
+                           E, sslots);
 }
 
 int launch_triplet_packed(const MapGeom &g, const float *X, int64_t n, int64_t ldx, float nu, float *E,
-                          unsigned long long *sslots, hipStream_t s) {
-    prof_begin(K_TRIP_PACKED, s);
-    for_each_launch(g, [&](auto M, const MapGeom &gg) { go_packed<decltype(M)::value>(gg, X, n, ldx, nu, E, sslots, s); });
-    prof_end(K_TRIP_PACKED, s);
+                          unsigned long long *sslots, bool tiled, hipStream_t s) {
+    const int kid = tiled ? K_TRIP_TILED : K_TRIP_PACKED;
+    prof_begin(kid, s);
+    for_each_launch(g, [&](auto M, const MapGeom &gg) {
+        constexpr int MAPK = decltype(M)::value;
+        if (tiled) go_packed<MAPK, true>(gg, X, n, ldx, nu, E, sslots, s);
+        else go_packed<MAPK, false>(gg, X, n, ldx, nu, E, sslots, s);
+    });
+    prof_end(kid, s);
     return check_launch("triplet packed");
 }
 

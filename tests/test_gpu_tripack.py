@@ -110,3 +110,46 @@ def test_packed_full_size_n2048():
     assert worst <= TOL
     e_tot = smx.triplet_energy(Xt, smx.Pot(nu=1.0, at=True, lj=False), "lambda")[1].item()
     assert abs(E.double().sum().item() - e_tot) <= 1e-5 * abs(e_tot)
+
+
+def _tiled_offsets(i, j, k):
+    X, Y, Z = i // 32, j // 32, k // 32
+    rank = Z * (Z + 1) * (Z + 2) // 6 + Y * (Y + 1) // 2 + X
+    return rank * 32768 + (i % 32) * 1024 + (j % 32) * 32 + (k % 32)
+
+
+@pytest.mark.parametrize("n", [3, 5, 31, 32, 33, 64, 65, 100])
+def test_tiled_layout_matches_packed_bit_for_bit(n):
+    """The tile-contiguous layout holds the packed values at the documented
+    offsets, bit for bit, and zeros everywhere else, on every map."""
+    X = synth.rsa(n, seed=60 + n, side=max(2.0, 0.9 * n ** (1 / 3)), dmin=0.6)
+    Xt = torch.from_numpy(X).cuda()
+    P = smx.triplet_packed(Xt, 0.7, "lambda").cpu().numpy()
+    i, j, k = _lex_triplets(n)
+    off = _tiled_offsets(i, j, k)
+    for kind in KINDS:
+        T, s = smx.triplet_packed_tiled(Xt, 0.7, kind, stats=True)
+        T = T.cpu().numpy()
+        assert T.shape[0] == smx.triplet_tiled_len(n)
+        np.testing.assert_array_equal(T[off], P)
+        rest = np.ones(T.shape[0], bool)
+        rest[off] = False
+        assert (T[rest] == 0).all()
+        assert int(s[0].item()) == math.comb(n, 3)
+
+
+def test_tiled_layout_full_size_rows():
+    """n = 2048: sampled rows of the tiled output equal the packed output."""
+    X = synth.workload_input("at_n2048")
+    n = X.shape[0]
+    Xt = torch.from_numpy(X).cuda()
+    P = smx.triplet_packed(Xt, 1.0, "lambda")
+    T = smx.triplet_packed_tiled(Xt, 1.0, "lambda")
+    torch.cuda.synchronize()
+    c3 = math.comb(n, 3)
+    for i in [0, 31, 32, 1000, n - 3]:
+        a = c3 - math.comb(n - i, 3)
+        m = math.comb(n - 1 - i, 2)
+        ii, jj, kk = _lex_triplets(n, i, i + 1)
+        off = torch.from_numpy(_tiled_offsets(ii, jj, kk)).cuda()
+        assert torch.equal(T[off], P[a:a + m])
