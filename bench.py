@@ -197,13 +197,33 @@ def main():
         ms32, c32 = smx.profile_read("edm_gram")
         smx.profile_enable(False)
         del X3s
+        # the tile-contiguous layout (one 64 KB run per 128 x 128 tile), plain and split
+        log("tile-contiguous EDM layout")
+        Dt = torch.empty(smx.edm_tiled_len(N_GRAM), dtype=torch.float32, device=dev)
+        tiled = {}
+        for prec in ("bf16", "split_bf16"):
+            smx.edm_tiled(X3, "lambda", prec, out=Dt, ws=ws3)
+            torch.cuda.synchronize()
+            smx.profile_enable(True)
+            smx.profile_reset()
+            for _ in range(args.steps):
+                smx.edm_tiled(X3, "lambda", prec, out=Dt, ws=ws3)
+            mt, ct = smx.profile_read("edm_gram")
+            smx.profile_enable(False)
+            tt = mt / ct / 1e3
+            bt = 4 * Dt.numel()
+            tiled[prec] = {"kernel_ms": tt * 1e3, "elements_per_s": e / tt, "bytes_written": bt,
+                           "hbm_gbs": bt / tt / 1e9, "hbm_frac": bt / tt / PEAK_HBM,
+                           "mfma_frac": (3 if prec == "split_bf16" else 1) * 2 * D_GRAM * e / tt / PEAK_BF16}
+        del Dt
         comps["edm_bf16_n32768_d512"] = {
             "elements": e, "kernel_ms": ms / c, "elements_per_s": e / t,
             "mfma_tflops": 2 * D_GRAM * e / t / 1e12, "mfma_frac": 2 * D_GRAM * e / t / PEAK_BF16,
             "hbm_gbs": byts / t / 1e9, "hbm_frac": byts / t / PEAK_HBM,
             "write_ceiling_fill_gbs": 4 * e / t_fill / 1e9,
             "write_ceiling_packed_d32_ms": ms32 / c32,
-            "frac_of_packed_d32": (ms32 / c32) / (ms / c)}
+            "frac_of_packed_d32": (ms32 / c32) / (ms / c),
+            "tiled_layout": tiled}
     if "at" in only:
         t = kavg["triplet_grad"] / 1e3
         tri = math.comb(N_AT, 3)

@@ -227,6 +227,16 @@ int smx_simplex_count(int m, int64_t n, int rho, int map, int strict, int64_t *d
 int smx_edm_packed(const float *d_X, int64_t n, int64_t d, int64_t ldx, int map, int prec,
                    float *d_D, void *d_ws, size_t ws_bytes, int64_t *d_stats, void *stream);
 
+/* The same squared distances in a tile-contiguous layout: 128 x 128 tiles for
+ * every precision, nb = ceil(n / 128), d_D of nb(nb+1)/2 * 16384 floats; tile
+ * (X, Y), X <= Y < nb, starts at (Y(Y+1)/2 + X) * 16384 and element (i, j) sits at
+ * 128 (i mod 128) + (j mod 128) of tile (i/128, j/128); entries of a tile that
+ * are not pairs i <= j < n are 0.  Each tile is one contiguous 64 KB run, so
+ * the stores stream.  Values are those of smx_edm_packed with the same `prec`,
+ * bit for bit.  Arguments, workspace and errors as smx_edm_packed. */
+int smx_edm_tiled(const float *d_X, int64_t n, int64_t d, int64_t ldx, int map, int prec, float *d_D,
+                  void *d_ws, size_t ws_bytes, int64_t *d_stats, void *stream);
+
 /* Triplet + pair interaction energy on the 3-simplex (Sec. I: the
  * triple-interaction n-body problem) and the 2-simplex (pair n-body).
  *   E = nu sum_{i<j<k} (1 + 3 cos g_i cos g_j cos g_k) / (r_ij r_jk r_ik)^3     (at_on)

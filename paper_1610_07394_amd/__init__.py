@@ -16,7 +16,7 @@ import torch
 
 __all__ = [
     "MAPS", "PRECS", "SmxError", "Pot", "lib", "volume", "parallel_blocks", "map_tiles_host", "map_blocks_host",
-    "workspace_bytes", "simplex_map2", "simplex_map3", "simplex_map4", "simplex_count", "triplet_packed", "triplet_packed_tiled", "triplet_tiled_len", "quad_contacts", "edm_packed", "triplet_energy",
+    "workspace_bytes", "simplex_map2", "simplex_map3", "simplex_map4", "simplex_count", "triplet_packed", "triplet_packed_tiled", "triplet_tiled_len", "edm_tiled", "edm_tiled_len", "quad_contacts", "edm_packed", "triplet_energy",
     "triplet_energy_grad", "triplet_energy_backward", "TripletEnergy", "profile_enable",
     "profile_reset", "profile_read", "KERNELS", "select_library", "check_flags",
 ]
@@ -81,6 +81,7 @@ def lib():
             getattr(L, name).argtypes = [_i64, _i32, _i32, _i32, _vp, _vp, _vp, _sz, _vp]
         L.smx_simplex_count.argtypes = [_i32, _i64, _i32, _i32, _i32, _vp, _vp, _sz, _vp]
         L.smx_triplet_packed.argtypes = [_vp, _i64, _i64, _dbl, _i32, _vp, _vp, _sz, _vp, _vp]
+        L.smx_edm_tiled.argtypes = [_vp, _i64, _i64, _i64, _i32, _i32, _vp, _vp, _sz, _vp, _vp]
         L.smx_triplet_packed_tiled.argtypes = [_vp, _i64, _i64, _dbl, _i32, _vp, _vp, _sz, _vp, _vp]
         L.smx_quad_contacts.argtypes = [_vp, _i64, _i64, _dbl, _i32, _vp, _vp, _sz, _vp, _vp]
         L.smx_check_flags.argtypes = [ctypes.POINTER(ctypes.c_uint32), _i32]
@@ -244,6 +245,31 @@ def edm_packed(X: torch.Tensor, map="lambda", prec="fp32", stats=False, out=None
         ws = _ws(need, X.device)
     _check(lib().smx_edm_packed(_dev(X, "X"), n, d, ldx, _map(map), p, _ptr(D), _ptr(ws),
                                 0 if ws is None else ws.numel(), _ptr(s), _stream()))
+    return (D, s) if stats else D
+
+
+def edm_tiled_len(n: int) -> int:
+    """Floats of the tile-contiguous EDM layout: nb(nb+1)/2 tiles of 128 x 128."""
+    nb = -(-n // 128)
+    return nb * (nb + 1) // 2 * 16384
+
+
+def edm_tiled(X: torch.Tensor, map="lambda", prec="fp32", stats=False, out=None, ws=None):
+    """Squared distances of the rows of X in the tile-contiguous layout (FP32
+    [edm_tiled_len(n)], see smx_edm_tiled)."""
+    if X.dtype != torch.float32 or X.dim() != 2 or X.stride(1) != 1:
+        raise ValueError("X must be a row-major FP32 matrix")
+    n, d = X.shape
+    ldx = X.stride(0) if n > 0 else d
+    p = PRECS[prec] if isinstance(prec, str) else int(prec)
+    D = out if out is not None else torch.empty(edm_tiled_len(n), dtype=torch.float32, device=X.device)
+    if D.dtype != torch.float32 or D.numel() < edm_tiled_len(n) or not D.is_contiguous():
+        raise ValueError("out must be a contiguous FP32 tensor of edm_tiled_len(n) elements")
+    s = torch.zeros(4, dtype=torch.int64, device=X.device) if stats else None
+    if ws is None and (p != 0 or stats):
+        ws = _ws(workspace_bytes(1, n, d, p, map), X.device)
+    _check(lib().smx_edm_tiled(_dev(X, "X"), n, d, ldx, _map(map), p, _ptr(D), _ptr(ws),
+                               0 if ws is None else ws.numel(), _ptr(s), _stream()))
     return (D, s) if stats else D
 
 

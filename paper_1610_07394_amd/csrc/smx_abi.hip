@@ -380,7 +380,7 @@ int smx_simplex_count(int m, int64_t n, int rho, int map, int strict, int64_t *d
     return launch_stats_finalize(slots, g.G, d_stats, S(stream));
 }
 
-int smx_edm_packed(const float *d_X, int64_t n, int64_t d, int64_t ldx, int map, int prec, float *d_D,
+static int edm_run(bool tiled, const float *d_X, int64_t n, int64_t d, int64_t ldx, int map, int prec, float *d_D,
                    void *d_ws, size_t ws_bytes, int64_t *d_stats, void *stream) {
     if (n < 0) return fail(SMX_EINVAL, "n must be >= 0");
     if (n > kMaxN) return fail(SMX_EOVERFLOW, "n exceeds 2^31 - 1");
@@ -394,7 +394,7 @@ int smx_edm_packed(const float *d_X, int64_t n, int64_t d, int64_t ldx, int map,
     const bool need_ws = prec != SMX_EDM_FP32_DIFF || d_stats != nullptr;
     if (need_ws && (d_ws == nullptr || ws_bytes < w.total))
         return fail(SMX_EINVAL, "workspace of %zu bytes required (got %zu)", w.total, ws_bytes);
-    const int tile = prec == SMX_EDM_FP32_DIFF ? edm_diff_tile(n) : gram_tile(n);
+    const int tile = tiled ? kEdmTiledTile : prec == SMX_EDM_FP32_DIFF ? edm_diff_tile(n) : gram_tile(n);
     MapGeom g;
     if (!make_geom(2, (n + tile - 1) / tile, map, g)) return g_status;
     char *ws = reinterpret_cast<char *>(d_ws);
@@ -403,7 +403,7 @@ int smx_edm_packed(const float *d_X, int64_t n, int64_t d, int64_t ldx, int map,
     if (slots && (rc = launch_fill_u64(reinterpret_cast<uint64_t *>(slots), kSlotBytes / 8, S(stream))))
         return rc;
     if (prec == SMX_EDM_FP32_DIFF) {
-        rc = launch_edm_diff(g, tile, d_X, n, d, ldx, d_D, slots, S(stream));
+        rc = launch_edm_diff(g, tile, d_X, n, d, ldx, d_D, slots, tiled, S(stream));
     } else {
         const bool split = prec == SMX_EDM_SPLITBF16_GRAM;
         const int64_t dpad = (d + kGramK - 1) / kGramK * kGramK;
@@ -411,11 +411,21 @@ int smx_edm_packed(const float *d_X, int64_t n, int64_t d, int64_t ldx, int map,
         uint16_t *lo = reinterpret_cast<uint16_t *>(ws + w.lo);
         float *norms = reinterpret_cast<float *>(ws + w.norms);
         rc = launch_gram_prep(d_X, n, d, ldx, dpad, hi, lo, norms, split, S(stream));
-        if (rc == SMX_OK) rc = launch_edm_gram(g, tile, hi, lo, norms, n, dpad, split, d_D, slots, S(stream));
+        if (rc == SMX_OK) rc = launch_edm_gram(g, tile, hi, lo, norms, n, dpad, split, d_D, slots, tiled, S(stream));
     }
     if (rc) return rc;
     if (slots) return launch_stats_finalize(slots, g.G, d_stats, S(stream));
     return SMX_OK;
+}
+
+int smx_edm_packed(const float *d_X, int64_t n, int64_t d, int64_t ldx, int map, int prec, float *d_D,
+                   void *d_ws, size_t ws_bytes, int64_t *d_stats, void *stream) {
+    return edm_run(false, d_X, n, d, ldx, map, prec, d_D, d_ws, ws_bytes, d_stats, stream);
+}
+
+int smx_edm_tiled(const float *d_X, int64_t n, int64_t d, int64_t ldx, int map, int prec, float *d_D,
+                  void *d_ws, size_t ws_bytes, int64_t *d_stats, void *stream) {
+    return edm_run(true, d_X, n, d, ldx, map, prec, d_D, d_ws, ws_bytes, d_stats, stream);
 }
 
 static int check_pot(const smx_pot *pot) {

@@ -60,7 +60,9 @@ __device__ __forceinline__ void edm_stage(float *__restrict__ sm, const float *_
     }
 }
 
-template <int MAP, int MT, bool VEC, bool STATS>
+// TILED: the tile-contiguous layout (tile (X, Y) at rank Y(Y+1)/2 + X times T^2,
+// element (i, j) at (i mod T) T + (j mod T), entries outside i <= j < n zero).
+template <int MAP, int MT, bool VEC, bool STATS, bool TILED>
 __global__ __launch_bounds__(kEdmThreads, 3) void edm_diff_kernel(MapGeom g, const float *__restrict__ X,
                                                                int64_t n, int64_t d, int64_t ldx,
                                                                float *__restrict__ D,
@@ -112,6 +114,20 @@ __global__ __launch_bounds__(kEdmThreads, 3) void edm_diff_kernel(MapGeom g, con
 
     // a tile off the diagonal and inside n (nearly every block) stores unmasked
     const bool interior = !diag && r0 + T <= n && c0 + T <= n;
+    if (TILED) {
+        const uint64_t rank = uint64_t(TY) * (uint64_t(TY) + 1) / 2 + uint64_t(TX);
+        float *tileD = D + rank * uint64_t(T * T) + tx;
+#pragma unroll
+        for (int r = 0; r < MT; ++r) {
+            const int64_t i = r0 + ty + 16 * r;
+            float *row = tileD + (ty + 16 * r) * T;
+#pragma unroll
+            for (int c = 0; c < MT; ++c) {
+                const int64_t j = c0 + tx + 16 * c;
+                row[16 * c] = (interior || (i < n && j < n && j >= i)) ? acc[r][c] : 0.f;
+            }
+        }
+    } else {
 #pragma unroll
     for (int r = 0; r < MT; ++r) {
         const int64_t i = r0 + ty + 16 * r;
@@ -125,6 +141,7 @@ __global__ __launch_bounds__(kEdmThreads, 3) void edm_diff_kernel(MapGeom g, con
                 row[16 * c] = acc[r][c];
         }
     }
+    }
     if (STATS) {
         __shared__ unsigned long long red[2][kEdmThreads / kWave];
         unsigned long long cnt, cs;
@@ -135,35 +152,40 @@ __global__ __launch_bounds__(kEdmThreads, 3) void edm_diff_kernel(MapGeom g, con
     }
 }
 
-template <int MAP, int MT, bool VEC>
+template <int MAP, int MT, bool VEC, bool TILED>
 static void go_edm(const MapGeom &g, const float *X, int64_t n, int64_t d, int64_t ldx, float *D,
                    unsigned long long *slots, hipStream_t s) {
     const dim3 grid = MAP == MAP_BBOX ? dim3(g.nb, g.nb, 1) : grid_for(g.G, kEdmThreads);
     if (slots)
-        hipLaunchKernelGGL((edm_diff_kernel<MAP, MT, VEC, true>), grid, dim3(kEdmThreads), 0, s, g, X, n, d,
-                           ldx, D, slots);
+        hipLaunchKernelGGL((edm_diff_kernel<MAP, MT, VEC, true, TILED>), grid, dim3(kEdmThreads), 0, s, g, X, n,
+                           d, ldx, D, slots);
     else
-        hipLaunchKernelGGL((edm_diff_kernel<MAP, MT, VEC, false>), grid, dim3(kEdmThreads), 0, s, g, X, n, d,
-                           ldx, D, slots);
+        hipLaunchKernelGGL((edm_diff_kernel<MAP, MT, VEC, false, TILED>), grid, dim3(kEdmThreads), 0, s, g, X, n,
+                           d, ldx, D, slots);
 }
 
 template <int MAP>
-static void go_edm_map(const MapGeom &g, int tile, bool vec, const float *X, int64_t n, int64_t d, int64_t ldx,
-                       float *D, unsigned long long *slots, hipStream_t s) {
-    if (tile == 128) {
-        if (vec) go_edm<MAP, 8, true>(g, X, n, d, ldx, D, slots, s);
-        else go_edm<MAP, 8, false>(g, X, n, d, ldx, D, slots, s);
+static void go_edm_map(const MapGeom &g, int tile, bool vec, bool tiled, const float *X, int64_t n, int64_t d,
+                       int64_t ldx, float *D, unsigned long long *slots, hipStream_t s) {
+    if (tiled) {  // the tile-contiguous layout uses 128-wide tiles at every n
+        if (vec) go_edm<MAP, 8, true, true>(g, X, n, d, ldx, D, slots, s);
+        else go_edm<MAP, 8, false, true>(g, X, n, d, ldx, D, slots, s);
+    } else if (tile == 128) {
+        if (vec) go_edm<MAP, 8, true, false>(g, X, n, d, ldx, D, slots, s);
+        else go_edm<MAP, 8, false, false>(g, X, n, d, ldx, D, slots, s);
     } else {
-        if (vec) go_edm<MAP, 4, true>(g, X, n, d, ldx, D, slots, s);
-        else go_edm<MAP, 4, false>(g, X, n, d, ldx, D, slots, s);
+        if (vec) go_edm<MAP, 4, true, false>(g, X, n, d, ldx, D, slots, s);
+        else go_edm<MAP, 4, false, false>(g, X, n, d, ldx, D, slots, s);
     }
 }
 
 int launch_edm_diff(const MapGeom &g, int tile, const float *X, int64_t n, int64_t d, int64_t ldx, float *D,
-                    unsigned long long *slots, hipStream_t s) {
+                    unsigned long long *slots, bool tiled, hipStream_t s) {
     const bool vec = (ldx % 4 == 0) && (d % kEdmKc == 0) && ((reinterpret_cast<uintptr_t>(X) & 15) == 0);
     prof_begin(K_EDM_DIFF, s);
-    for_each_launch(g, [&](auto M, const MapGeom &gg) { go_edm_map<decltype(M)::value>(gg, tile, vec, X, n, d, ldx, D, slots, s); });
+    for_each_launch(g, [&](auto M, const MapGeom &gg) {
+        go_edm_map<decltype(M)::value>(gg, tile, vec, tiled, X, n, d, ldx, D, slots, s);
+    });
     prof_end(K_EDM_DIFF, s);
     return check_launch("edm_packed (fp32 diff)");
 }

@@ -173,7 +173,9 @@ __device__ __forceinline__ void lds_wait(bf16x8_t (&a)[NP][MT], bf16x8_t (&b)[NP
         for (int m = 0; m < MT; ++m) asm volatile("" : "+v"(a[p][m]), "+v"(b[p][m]));
 }
 
-template <int MAP, bool SPLIT, bool STATS, int WT>
+// TILED: the tile-contiguous layout (tile (X, Y) at rank Y(Y+1)/2 + X times T^2,
+// element (i, j) at (i mod T) T + (j mod T), entries outside i <= j < n zero).
+template <int MAP, bool SPLIT, bool STATS, int WT, bool TILED>
 __global__ __launch_bounds__(kGramThreads) void edm_gram_kernel(MapGeom g, const uint16_t *__restrict__ hi,
                                                                const uint16_t *__restrict__ lo,
                                                                const float *__restrict__ norms,
@@ -280,6 +282,19 @@ __global__ __launch_bounds__(kGramThreads) void edm_gram_kernel(MapGeom g, const
             const int rl = it * (64 / LPR) + lane / LPR, cl = 4 * (lane % LPR);
             const int64_t i = I0 + wm * WT + m * 32 + rl, j = J0 + wn * WT + cl;
             const float4 v = *reinterpret_cast<const float4 *>(St + rl * WT + cl);
+            if (TILED) {
+                const uint64_t rank = uint64_t(TY) * (uint64_t(TY) + 1) / 2 + uint64_t(TX);
+                float *tdst = D + rank * uint64_t(T * T) + uint64_t(i - I0) * T + uint64_t(j - J0);
+                float4 o = v;
+                if (!interior) {
+                    o.x = (i < n && j + 0 < n && j + 0 >= i) ? v.x : 0.f;
+                    o.y = (i < n && j + 1 < n && j + 1 >= i) ? v.y : 0.f;
+                    o.z = (i < n && j + 2 < n && j + 2 >= i) ? v.z : 0.f;
+                    o.w = (i < n && j + 3 < n && j + 3 >= i) ? v.w : 0.f;
+                }
+                *reinterpret_cast<float4 *>(tdst) = o;  // 16-byte aligned: tiles start at multiples of T^2
+                continue;
+            }
             float *dst = D + (i * n - (i * (i - 1)) / 2 - i) + j;
             if (interior) {
                 if (smx_check(i < n && j >= i && j + 3 < n, kCheckStore))
@@ -302,27 +317,33 @@ __global__ __launch_bounds__(kGramThreads) void edm_gram_kernel(MapGeom g, const
     }
 }
 
-template <int MAP, bool SPLIT, int WT>
+template <int MAP, bool SPLIT, int WT, bool TILED>
 static void go_gram(const MapGeom &g, const uint16_t *hi, const uint16_t *lo, const float *norms,
                     int64_t n, int64_t dpad, float *D, unsigned long long *slots, hipStream_t s) {
     const dim3 grid = MAP == MAP_BBOX ? dim3(g.nb, g.nb, 1) : grid_for(g.G, kGramThreads);
     if (slots)
-        hipLaunchKernelGGL((edm_gram_kernel<MAP, SPLIT, true, WT>), grid, dim3(kGramThreads), 0, s, g, hi, lo,
-                           norms, n, dpad, D, slots);
+        hipLaunchKernelGGL((edm_gram_kernel<MAP, SPLIT, true, WT, TILED>), grid, dim3(kGramThreads), 0, s, g, hi,
+                           lo, norms, n, dpad, D, slots);
     else
-        hipLaunchKernelGGL((edm_gram_kernel<MAP, SPLIT, false, WT>), grid, dim3(kGramThreads), 0, s, g, hi, lo,
-                           norms, n, dpad, D, slots);
+        hipLaunchKernelGGL((edm_gram_kernel<MAP, SPLIT, false, WT, TILED>), grid, dim3(kGramThreads), 0, s, g, hi,
+                           lo, norms, n, dpad, D, slots);
 }
 
 int launch_edm_gram(const MapGeom &g, int tile, const uint16_t *hi, const uint16_t *lo, const float *norms,
-                    int64_t n, int64_t dpad, bool split, float *D, unsigned long long *slots,
+                    int64_t n, int64_t dpad, bool split, float *D, unsigned long long *slots, bool tiled,
                     hipStream_t s) {
     prof_begin(K_EDM_GRAM, s);
     for_each_launch(g, [&](auto M, const MapGeom &gg) {
         constexpr int MAPK = decltype(M)::value;
+        constexpr int WT = kGramTile / 2;
         (void)tile;  // kGramTile
-        if (split) go_gram<MAPK, true, kGramTile / 2>(gg, hi, lo, norms, n, dpad, D, slots, s);
-        else go_gram<MAPK, false, kGramTile / 2>(gg, hi, lo, norms, n, dpad, D, slots, s);
+        if (tiled) {
+            if (split) go_gram<MAPK, true, WT, true>(gg, hi, lo, norms, n, dpad, D, slots, s);
+            else go_gram<MAPK, false, WT, true>(gg, hi, lo, norms, n, dpad, D, slots, s);
+        } else {
+            if (split) go_gram<MAPK, true, WT, false>(gg, hi, lo, norms, n, dpad, D, slots, s);
+            else go_gram<MAPK, false, WT, false>(gg, hi, lo, norms, n, dpad, D, slots, s);
+        }
     });
     prof_end(K_EDM_GRAM, s);
     return check_launch("edm_packed (gram)");

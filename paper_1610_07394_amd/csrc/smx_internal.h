@@ -133,16 +133,17 @@ int launch_count(int m, const MapGeom &g, int64_t n, int rho, int map, int stric
 // enough of them to fill the chip, 64 x 64 (4 x 4 per thread) below that.
 inline int edm_diff_tile(int64_t n) { return n >= 8192 ? 128 : 64; }
 constexpr int kGramTile = 128;   // Gram form: 128 x 128 elements per block
+constexpr int kEdmTiledTile = 128;  // tile edge of the tile-contiguous EDM layout (every precision)
 inline int gram_tile(int64_t) { return kGramTile; }
 constexpr int kGramK = 32;       // Gram K padding
 // rows of the fragment-ordered BF16 operands (zero padded to a 32-row block)
 __host__ __device__ inline int64_t gram_rows(int64_t n) { return (n + 31) / 32 * 32; }
 int launch_edm_diff(const MapGeom &g, int tile, const float *X, int64_t n, int64_t d, int64_t ldx, float *D,
-                    unsigned long long *slots, hipStream_t s);
+                    unsigned long long *slots, bool tiled, hipStream_t s);
 int launch_gram_prep(const float *X, int64_t n, int64_t d, int64_t ldx, int64_t dpad, uint16_t *hi,
                      uint16_t *lo, float *norms, bool split, hipStream_t s);
 int launch_edm_gram(const MapGeom &g, int tile, const uint16_t *hi, const uint16_t *lo, const float *norms,
-                    int64_t n, int64_t dpad, bool split, float *D, unsigned long long *slots,
+                    int64_t n, int64_t dpad, bool split, float *D, unsigned long long *slots, bool tiled,
                     hipStream_t s);
 
 constexpr int kTripTile = 32;    // Axilrod-Teller: 32^3 triplets per block

@@ -205,3 +205,46 @@ def test_edm_gram_large_n_ragged(prec):
             worst = max(worst, float((np.abs(got[1:] - ref[1:]) / (nrm[i] + nrm[i + 1:])).max()))
     print(f"  {prec}: max error {worst:.3e}")
     assert worst <= TOL[prec]
+
+
+def _tiled_edm_offsets(i, j):
+    X, Y = i // 128, j // 128
+    return (Y * (Y + 1) // 2 + X) * 16384 + (i % 128) * 128 + (j % 128)
+
+
+@pytest.mark.parametrize("n,d", [(1, 3), (5, 1), (127, 3), (128, 8), (129, 33), (300, 64), (1100, 40)])
+@pytest.mark.parametrize("prec", ["fp32", "bf16", "split_bf16"])
+def test_edm_tiled_layout_matches_packed(n, d, prec):
+    """The tile-contiguous layout holds the packed values at the documented
+    offsets, bit for bit, and zeros elsewhere, on every map."""
+    X = synth.normal(n, d, seed=3 * n + d)
+    Xt = torch.from_numpy(X).cuda()
+    P = smx.edm_packed(Xt, "lambda", prec).cpu().numpy()
+    ii = np.concatenate([np.full(n - i, i) for i in range(n)])
+    jj = np.concatenate([np.arange(i, n) for i in range(n)])
+    off = _tiled_edm_offsets(ii, jj)
+    for kind in KINDS:
+        T = smx.edm_tiled(Xt, kind, prec).cpu().numpy()
+        assert T.shape[0] == smx.edm_tiled_len(n)
+        np.testing.assert_array_equal(T[off], P)
+        rest = np.ones(T.shape[0], bool)
+        rest[off] = False
+        assert (T[rest] == 0).all()
+
+
+@pytest.mark.parametrize("prec", ["fp32", "split_bf16"])
+def test_edm_tiled_full_size_rows(prec):
+    """Full-size inputs (n = 65536, d = 64 FP32; n = 32768, d = 512 split BF16):
+    sampled rows of the tiled output equal the packed output."""
+    name = "edm_n65536_d64" if prec == "fp32" else "gram_n32768_d512"
+    X = synth.workload_input(name)
+    n = X.shape[0]
+    Xt = torch.from_numpy(X).cuda()
+    P = smx.edm_packed(Xt, "lambda", prec)
+    T = smx.edm_tiled(Xt, "lambda", prec)
+    torch.cuda.synchronize()
+    for i in [0, 127, 128, n // 2 + 5, n - 1]:
+        a = i * n - i * (i - 1) // 2
+        jj = np.arange(i, n)
+        off = torch.from_numpy(_tiled_edm_offsets(np.full(n - i, i), jj)).cuda()
+        assert torch.equal(T[off], P[a:a + n - i])
