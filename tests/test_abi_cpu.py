@@ -158,6 +158,18 @@ def test_validation_errors_before_any_device_work():
     assert L.smx_quad_contacts(ctypes.c_void_p(256), 10, 3, 1.0, 0, ctypes.c_void_p(256), null, 0, null,
                                null) == 1
     assert b"workspace" in L.smx_last_error()
+    # tile-contiguous layouts share the checks of their packed forms
+    assert L.smx_triplet_packed_tiled(null, (1 << 21) + 1, 3, 1.0, 0, null, null, 0, null, null) == 2
+    assert L.smx_triplet_packed_tiled(null, 10, 3, 1.0, 7, null, null, 0, null, null) == 1
+    assert L.smx_triplet_packed_tiled(null, 10, 3, 1.0, 0, null, null, 0, null, null) == 1
+    assert L.smx_edm_tiled(null, 10, 0, 3, 0, 0, null, null, 0, null, null) == 1
+    assert L.smx_edm_tiled(null, 10, 3, 3, 0, 9, null, null, 0, null, null) == 1
+    assert L.smx_edm_tiled(ctypes.c_void_p(256), 10, 3, 3, 0, 1, ctypes.c_void_p(256), null, 0, null, null) == 1
+    assert L.smx_edm_tiled(null, 0, 3, 3, 0, 0, null, null, 0, null, null) == 0
+    # probe: NULL output, block count, iterations
+    assert L.smx_probe_valu(null, 1, 1, null) == 1
+    assert L.smx_probe_valu(ctypes.c_void_p(256), 0, 1, null) == 1
+    assert L.smx_probe_valu(ctypes.c_void_p(256), 1, 0, null) == 1
     # EDM argument checks
     assert L.smx_edm_packed(null, 10, 0, 3, 0, 0, null, null, 0, null, null) == 1
     assert L.smx_edm_packed(null, 10, 3, 2, 0, 0, null, null, 0, null, null) == 1
