@@ -501,8 +501,25 @@ def cpu_baseline(only, elements, total_elems):
         secs_per_step += tri * dt_e / tri_e + tri * dt_g / tri_g + dt_lj
         samples.append(f"AT energy i<{i1} ({tri_e} triplets, {dt_e:.2f}s); AT gradient of {len(rows)} particles "
                        f"({tri_g} triplets, {dt_g:.2f}s); LJ energy+gradient full ({dt_lj:.2f}s)")
+    # one core, for reference: the FP32-input EDM rows and the AT energy on small samples
+    single = {}
+    oracle.set_threads(1)
+    try:
+        if "edm" in only:
+            X = synth.workload_input("edm_n65536_d64")
+            t0 = time.perf_counter()
+            oracle.edm_rows(X, 0, 512)
+            single["edm_pairs_per_s"] = oracle.packed_offset(512, N_EDM) / (time.perf_counter() - t0)
+        if "at" in only:
+            X = synth.workload_input("at_lj_n8192")
+            t0 = time.perf_counter()
+            oracle.at_energy(X, 1.0, 0, 4)
+            single["at_energy_triplets_per_s"] = (sum(math.comb(N_AT - 1 - i, 2) for i in range(4))
+                                                  / (time.perf_counter() - t0))
+    finally:
+        oracle.set_threads(cores)
     return {"value": total_elems / secs_per_step, "unit": "elements/s", "cores": cores, "kind": "oracle",
-            "sample": "; ".join(samples) + " -- scaled to one full step"}
+            "sample": "; ".join(samples) + " -- scaled to one full step", "single_core": single}
 
 
 if __name__ == "__main__":

@@ -61,6 +61,7 @@ def lib():
     if _lib is None:
         L = ctypes.CDLL(build())
         L.orc_max_threads.restype = ctypes.c_int
+        L.orc_set_threads.argtypes = [ctypes.c_int]
         L.orc_edm_rows.argtypes = [_ptr, _i64, _i64, _i64, _i64, _i64, _ptr]
         L.orc_edm_pairs.argtypes = [_ptr, _i64, _i64, _ptr, _ptr, _i64, _ptr]
         L.orc_at_energy.argtypes = [_ptr, _i64, _i64, _dbl, _i64, _i64]
@@ -87,6 +88,11 @@ def _f32(X: np.ndarray) -> np.ndarray:
     X = np.ascontiguousarray(X, dtype=np.float32)
     assert X.ndim == 2
     return X
+
+
+def set_threads(k: int) -> None:
+    """Thread count of the oracle's parallel loops from now on."""
+    lib().orc_set_threads(int(k))
 
 
 def threads() -> int:

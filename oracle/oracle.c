@@ -26,6 +26,9 @@
 
 int orc_max_threads(void) { return omp_get_max_threads(); }
 
+/* Thread count for the parallel loops that follow (for single-core timings). */
+void orc_set_threads(int k) { omp_set_num_threads(k > 0 ? k : 1); }
+
 /* ------------------------------------------------------------------------ */
 /* Packed Euclidean distance matrix (paper Sec. I and II: the EDM is a
  * 2-simplex problem; only the upper triangle is needed).  Output layout: the
