@@ -18,6 +18,8 @@ library computes, written from the paper (Navarro, Bustos, Hitschfeld,
 * ``lj_energy`` / ``lj_grad`` -- Lennard-Jones pair energy and gradient.
 * ``quad_contacts`` -- 4-point contacts (4-cliques of the contact graph) on
                        the 4-simplex, by neighbour-list intersection.
+* ``life_step`` / ``life_window`` -- Conway's Life on the 2-simplex of cells
+                       (a cellular automaton on a triangular domain, Sec. I).
 * ``checksum_range`` / ``checksum_walk`` -- element-id checksums.
 
 Only ``tests/``, ``__graft_entry__.smoke()`` and the benchmark's CPU-baseline
@@ -181,6 +183,45 @@ def quad_contacts(X: np.ndarray, rc: float) -> int:
     below fl(rc^2)): the 4-cliques of the contact graph."""
     X = _f32(X)
     return int(lib().orc_quad_contacts(X.ctypes.data, X.shape[0], X.shape[1], rc))
+
+
+def life_step(S: np.ndarray) -> np.ndarray:
+    """One generation of Conway's Life (birth on 3 neighbours, survival on 2 or
+    3, Moore neighbourhood) on the discrete orthogonal 2-simplex of cells
+    (i, j), 0 <= i <= j < n: cells outside it are dead and stay dead.  S is a
+    dense n x n uint8 grid; the result is one too, 0 below the diagonal."""
+    n = S.shape[0]
+    inside = np.triu(np.ones((n, n), dtype=bool))
+    alive = (S != 0) & inside
+    P = np.pad(alive, 1).astype(np.uint8)
+    count = np.zeros((n, n), dtype=np.uint8)
+    for di in (-1, 0, 1):
+        for dj in (-1, 0, 1):
+            if di or dj:
+                count += P[1 + di:1 + di + n, 1 + dj:1 + dj + n]
+    new = ((count == 3) | (alive & (count == 2))) & inside
+    return new.astype(np.uint8)
+
+
+def life_window(S: np.ndarray, i0: int, i1: int, j0: int, j1: int) -> np.ndarray:
+    """Cells [i0, i1) x [j0, j1) of life_step(S), computed from that window of S
+    and a one-cell ring around it (cells past the grid count as dead)."""
+    n = S.shape[0]
+    a0, a1, b0, b1 = max(i0 - 1, 0), min(i1 + 1, n), max(j0 - 1, 0), min(j1 + 1, n)
+    W = np.zeros((a1 - a0 + 2, b1 - b0 + 2), dtype=np.uint8)
+    W[1:-1, 1:-1] = S[a0:a1, b0:b1]
+    ii = np.arange(a0 - 1, a1 + 1)[:, None]
+    jj = np.arange(b0 - 1, b1 + 1)[None, :]
+    inside = (ii <= jj) & (ii >= 0) & (jj < n)
+    alive = (W != 0) & inside
+    count = np.zeros((W.shape[0] - 2, W.shape[1] - 2), dtype=np.uint8)
+    for di in (-1, 0, 1):
+        for dj in (-1, 0, 1):
+            if di or dj:
+                count += alive[1 + di:W.shape[0] - 1 + di, 1 + dj:W.shape[1] - 1 + dj]
+    core = alive[1:-1, 1:-1]
+    new = ((count == 3) | (core & (count == 2))) & inside[1:-1, 1:-1]
+    return new.astype(np.uint8)[i0 - a0:i1 - a0, j0 - b0:j1 - b0]
 
 
 def mix64(x: int) -> int:

@@ -14,7 +14,11 @@ Recipes (all seeded with ``numpy.random.default_rng(seed)``, PCG64):
   uniformly (FP64) in [0, side)^3 and kept only if their distance to every
   point kept so far is at least ``dmin``; the kept points are cast to FP32.
 
-``WORKLOADS`` lists the five workloads by what they are.
+* ``bits``     -- uint8 0/1 cells of an n x n grid, each 1 with probability
+  ``density`` (the initial states of the cellular automaton on the 2-simplex;
+  the consumer keeps the cells of its domain).
+
+``WORKLOADS`` lists the workloads by what they are.
 """
 from __future__ import annotations
 
@@ -22,7 +26,7 @@ import math
 
 import numpy as np
 
-__all__ = ["uniform", "normal", "integer", "rsa", "WORKLOADS", "workload_input"]
+__all__ = ["uniform", "normal", "integer", "rsa", "bits", "WORKLOADS", "workload_input"]
 
 
 def uniform(n: int, d: int, seed: int) -> np.ndarray:
@@ -38,6 +42,12 @@ def normal(n: int, d: int, seed: int) -> np.ndarray:
 def integer(n: int, d: int, seed: int, lo: int = -8, hi: int = 8) -> np.ndarray:
     rng = np.random.default_rng(seed)
     return rng.integers(lo, hi, size=(n, d)).astype(np.float32)
+
+
+def bits(n: int, seed: int, density: float = 0.3) -> np.ndarray:
+    rng = np.random.default_rng(seed)
+    thr = int(round(density * 256))
+    return (rng.integers(0, 256, size=(n, n), dtype=np.uint8) < thr).astype(np.uint8)
 
 
 def rsa(n: int, seed: int, side: float = 20.0, dmin: float = 0.8,

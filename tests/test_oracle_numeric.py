@@ -324,3 +324,71 @@ def test_quad_contacts_closed_forms():
     X = synth.uniform(60, 3, seed=5) * np.float32(4.0)
     p = np.random.default_rng(0).permutation(60)
     assert oracle.quad_contacts(X[p], 1.5) == oracle.quad_contacts(X, 1.5) > 0
+
+
+# --------------------------------------------------------------------------
+# Conway's Life on the 2-simplex of cells (i <= j): known patterns far from the
+# boundary behave as on the plane; the boundary kills what would leave the
+# triangle; cells below the diagonal never live.
+def _grid(n, cells):
+    S = np.zeros((n, n), np.uint8)
+    for i, j in cells:
+        S[i, j] = 1
+    return S
+
+
+def _cells(S):
+    return sorted(map(tuple, np.argwhere(S).tolist()))
+
+
+def test_life_blinker_period_two():
+    S = _grid(40, [(10, 29), (10, 30), (10, 31)])          # horizontal, inside the triangle
+    S1 = oracle.life_step(S)
+    assert _cells(S1) == [(9, 30), (10, 30), (11, 30)]     # vertical
+    assert (oracle.life_step(S1) == S).all()
+
+
+def test_life_still_lifes():
+    block = _grid(40, [(5, 20), (5, 21), (6, 20), (6, 21)])
+    assert (oracle.life_step(block) == block).all()
+    beehive = _grid(40, [(8, 21), (8, 22), (9, 20), (9, 23), (10, 21), (10, 22)])
+    assert (oracle.life_step(beehive) == beehive).all()
+
+
+def test_life_glider_moves_one_cell_diagonally_every_four_steps():
+    g = [(0, 1), (1, 2), (2, 0), (2, 1), (2, 2)]
+    S = _grid(60, [(5 + i, 30 + j) for i, j in g])
+    T = S
+    for _ in range(4):
+        T = oracle.life_step(T)
+    assert _cells(T) == [(6 + i, 31 + j) for i, j in sorted(g)]
+
+
+def test_life_boundary_cuts_patterns():
+    n = 30
+    # a vertical blinker on the last column: its horizontal phase would need
+    # column n, so two cells remain, and they die in the next step
+    S = _grid(n, [(9, n - 1), (10, n - 1), (11, n - 1)])
+    S1 = oracle.life_step(S)
+    assert _cells(S1) == [(10, n - 2), (10, n - 1)]
+    assert oracle.life_step(S1).sum() == 0
+    # a vertical blinker crossing the diagonal: its cell (11, 10) lies outside
+    # the triangle and does not count, the two cells left have one neighbour
+    # each and no cell has three, so everything dies at once
+    S = _grid(n, [(9, 10), (10, 10), (11, 10)])
+    assert oracle.life_step(S).sum() == 0
+    # the same blinker one column to the right lies inside and oscillates
+    S = _grid(n, [(9, 11), (10, 11), (11, 11)])
+    assert _cells(oracle.life_step(S)) == [(10, 10), (10, 11), (10, 12)]
+    # below the diagonal nothing ever lives, whatever the input holds there
+    R = synth.bits(64, 9, 0.5)
+    for _ in range(5):
+        R = oracle.life_step(R)
+        assert (np.tril(R, -1) == 0).all()
+
+
+def test_life_window_equals_full_step():
+    S = synth.bits(150, 4, 0.35)
+    A = oracle.life_step(S)
+    for (i0, i1, j0, j1) in [(0, 40, 0, 40), (20, 90, 60, 150), (100, 150, 100, 150), (0, 150, 0, 150)]:
+        assert (oracle.life_window(S, i0, i1, j0, j1) == A[i0:i1, j0:j1]).all()
