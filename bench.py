@@ -50,6 +50,7 @@ N_AT = 8192
 N_MAP4 = 1024  # 4-simplex map-only comparison: 8^4-element tiles, nb = 128
 ALL_MAPS = ("lambda", "bbox", "linear", "recursive", "recursive_launch")
 QUICK_MAPS = ("lambda", "bbox")
+N_LIFE = 32768  # Life on the 2-simplex: 512 x 512 tiles of 64 x 64 cells, upper triangle
 QUAD_RC = 2.0  # contact radius of the 4-point contact count (mean contact degree ~34)
 
 
@@ -309,6 +310,35 @@ def main():
             "speedup_lambda_vs_bbox": (qd["bbox"]["words_ms"] + qd["bbox"]["quad_ms"]) / (t * 1e3),
             "per_unit": "64^4 quadruplets per block; 3 KB of contact words read per block"}
         del ws4
+
+    # Life on the 2-simplex of cells, n = 32768, tile-contiguous 64 x 64 byte
+    # tiles (measured beside the step): one generation per launch, buffers alternated
+    if not args.no_compare:
+        log(f"life on the 2-simplex, n = {N_LIFE}")
+        ln = smx.life_len(N_LIFE)
+        La = torch.from_numpy(synth.bits_flat(ln, seed=31, density=0.3)).to(dev)
+        Lb = torch.empty_like(La)
+        lf = {}
+        for kind in QUICK_MAPS if args.quick_compare else ALL_MAPS:
+            smx.simplex_life(La, N_LIFE, kind, out=Lb)
+            torch.cuda.synchronize()
+            smx.profile_enable(True)
+            smx.profile_reset()
+            for s_ in range(args.steps):
+                src, dst = (La, Lb) if s_ % 2 == 0 else (Lb, La)
+                smx.simplex_life(src, N_LIFE, kind, out=dst)
+            ms, c = smx.profile_read("life")
+            smx.profile_enable(False)
+            lf[kind] = {"kernel_ms": ms / c, "blocks": smx.parallel_blocks(2, N_LIFE // 64, 1, kind)}
+        cells = N_LIFE * (N_LIFE + 1) // 2
+        t = lf["lambda"]["kernel_ms"] / 1e3
+        comps["life_n32768"] = {
+            "cells": cells, "ms": t * 1e3, "cells_per_s": cells / t, "hbm_gbs": 2 * ln / t / 1e9,
+            "hbm_frac": 2 * ln / t / PEAK_HBM, "maps": lf,
+            "speedup_lambda_vs_bbox": lf["bbox"]["kernel_ms"] / (t * 1e3),
+            "per_unit": "8192 bytes per 64 x 64 tile (4096 read, 4096 written; the 260-cell ring from "
+                        "neighbouring tiles not counted), 131328 tiles per launch"}
+        del La, Lb
 
     # dominant kernel (largest time per step)
     per_step = {k: kern[k][0] / args.steps for k in kern}

@@ -337,6 +337,21 @@ int smx_probe_valu(float *d_out, int64_t blocks, int iters, void *stream);
  * SMX_EUNSUPPORTED in the normal library (no checks compiled in). */
 int smx_check_flags(uint32_t *flags, int clear);
 
+/* One generation of Conway's Life on the 2-simplex of cells (i, j), 0 <= i <=
+ * j < n: a cellular automaton on a triangular domain (Sec. I).  Birth on 3 live
+ * neighbours, survival on 2 or 3 (Moore neighbourhood); cells outside the
+ * triangle are dead.  Tiles of 64 x 64 cells on the 2-simplex map `map`.
+ *   d_in, d_out  uint8 device buffers of nb(nb+1)/2 * 4096 bytes, nb = ceil(n/64),
+ *                tile-contiguous: tile (X, Y), X <= Y < nb, at (Y(Y+1)/2 + X) * 4096,
+ *                cell (i, j) at 64 (i mod 64) + (j mod 64), 1 = alive.  d_out gets 0
+ *                outside the triangle; d_in is not read there.  Distinct buffers
+ *                (a caller stepping several generations alternates them).
+ *   d_stats      int64[4] or NULL: [0] live cells after the step, [1] 0, [2] mapped
+ *                blocks, [3] launched blocks (d_ws of smx_workspace_bytes(0, ...)).
+ * n <= 2^24. */
+int smx_simplex_life(const uint8_t *d_in, uint8_t *d_out, int64_t n, int map, int64_t *d_stats, void *d_ws,
+                     size_t ws_bytes, void *stream);
+
 /* d_out[q] = gradE[0] * d_G[q] for q < 3n (FP32 out, FP64 scale): the backward
  * pass of smx_triplet_energy_grad's output, given the incoming gradient
  * d_gradE (FP64 device scalar).  d_out may alias d_G. */
@@ -347,7 +362,7 @@ int smx_scale_grad(const float *d_G, int64_t n, const double *d_gradE, float *d_
  * returns the summed duration (ms) and launch count of kernel `kernel_id`
  * (0 map2, 1 map3, 2 edm diff, 3 edm gram, 4 gram prep, 5 triplet energy,
  * 6 triplet grad, 7 lj, 8 finalize, 9 triplet packed, 10 map4, 11 contact words,
- * 12 quad contacts, 13 triplet packed tiled) since the last reset; it
+ * 12 quad contacts, 13 triplet packed tiled, 14 life) since the last reset; it
  * returns SMX_EINVAL
  * for an unknown id.  smx_profile_reset clears the totals.  Host only. */
 int smx_profile_enable(int on);

@@ -505,12 +505,32 @@ int smx_probe_valu(float *d_out, int64_t blocks, int iters, void *stream) {
     return launch_valu_probe(d_out, blocks, iters, S(stream));
 }
 
+int smx_simplex_life(const uint8_t *d_in, uint8_t *d_out, int64_t n, int map, int64_t *d_stats, void *d_ws,
+                     size_t ws_bytes, void *stream) {
+    if (n < 0) return fail(SMX_EINVAL, "n must be >= 0");
+    if (n > (int64_t(1) << 24)) return fail(SMX_EOVERFLOW, "n = %lld exceeds 2^24", (long long)n);
+    if (map < 0 || map > MAP_REC_LAUNCH) return fail(SMX_EINVAL, "unknown map %d", map);
+    if (n > 0 && (d_in == nullptr || d_out == nullptr)) return fail(SMX_EINVAL, "in and out must not be NULL");
+    if (n > 0 && d_in == d_out) return fail(SMX_EINVAL, "in and out must be different buffers");
+    if (d_stats != nullptr && (d_ws == nullptr || ws_bytes < kSlotBytes))
+        return fail(SMX_EINVAL, "statistics need a workspace of %zu bytes", kSlotBytes);
+    MapGeom g{};
+    if (n > 0 && !make_geom(2, (n + kLifeTile - 1) / kLifeTile, map, g)) return g_status;
+    unsigned long long *slots = d_stats ? reinterpret_cast<unsigned long long *>(d_ws) : nullptr;
+    int rc;
+    if (slots && (rc = launch_fill_u64(reinterpret_cast<uint64_t *>(slots), kSlotBytes / 8, S(stream)))) return rc;
+    if (n > 0 && (rc = launch_life(g, d_in, d_out, n, slots, S(stream)))) return rc;
+    if (slots) return launch_stats_finalize(slots, g.G, d_stats, S(stream));
+    return SMX_OK;
+}
+
 int smx_check_flags(uint32_t *flags, int clear) {
     if (flags == nullptr) return fail(SMX_EINVAL, "flags must not be NULL");
     if (!SMX_CHECKED) return fail(SMX_EUNSUPPORTED, "this library is built without device checks");
     const bool c = clear != 0;
-    const unsigned parts[] = {check_flags_edm(c), check_flags_gram(c), check_flags_map(c),
-                              check_flags_quad(c), check_flags_tripack(c), check_flags_triplet(c)};
+    const unsigned parts[] = {check_flags_edm(c),  check_flags_gram(c),    check_flags_map(c),
+                              check_flags_quad(c), check_flags_tripack(c), check_flags_triplet(c),
+                              check_flags_life(c)};
     unsigned v = 0;
     for (unsigned p : parts) {
         if (p == ~0u) return fail(SMX_EHIP, "reading the device check flags failed");

@@ -38,12 +38,13 @@ unsigned check_flags_map(bool clear);
 unsigned check_flags_quad(bool clear);
 unsigned check_flags_tripack(bool clear);
 unsigned check_flags_triplet(bool clear);
+unsigned check_flags_life(bool clear);
 
 // Kernel ids for the timing facility (match smx_profile_read).
 enum KernelId {
     K_MAP2 = 0, K_MAP3 = 1, K_EDM_DIFF = 2, K_EDM_GRAM = 3, K_GRAM_PREP = 4,
     K_TRIP_ENERGY = 5, K_TRIP_GRAD = 6, K_LJ = 7, K_FINALIZE = 8, K_TRIP_PACKED = 9, K_MAP4 = 10,
-    K_QUAD_WORDS = 11, K_QUAD = 12, K_TRIP_TILED = 13, K_COUNT = 14
+    K_QUAD_WORDS = 11, K_QUAD = 12, K_TRIP_TILED = 13, K_LIFE = 14, K_COUNT = 15
 };
 void prof_begin(int kid, hipStream_t s);
 void prof_end(int kid, hipStream_t s);
@@ -160,6 +161,9 @@ int launch_contact_words(const MapGeom &g, const float *X, int64_t n, int64_t ld
                          int64_t npad, hipStream_t s);
 int launch_quad(const MapGeom &g, const uint64_t *W, int64_t npad, int64_t n, unsigned long long *cslots,
                 unsigned long long *sslots, hipStream_t s);
+constexpr int kLifeTile = 64;    // cellular automaton: 64 x 64 cells per tile
+int launch_life(const MapGeom &g, const uint8_t *S, uint8_t *D, int64_t n, unsigned long long *slots,
+                hipStream_t s);
 int launch_count_finalize(const unsigned long long *slots, int64_t *out, hipStream_t s);
 int launch_valu_probe(float *out, int64_t blocks, int iters, hipStream_t s);
 int launch_grad_finalize(const double *G64, int64_t n, const double *gradE, float *out,

@@ -50,6 +50,14 @@ def bits(n: int, seed: int, density: float = 0.3) -> np.ndarray:
     return (rng.integers(0, 256, size=(n, n), dtype=np.uint8) < thr).astype(np.uint8)
 
 
+def bits_flat(count: int, seed: int, density: float = 0.3) -> np.ndarray:
+    """``count`` independent cells, 1 with probability ``density`` (in steps of
+    1/256), as a flat uint8 vector: a cell buffer in any layout."""
+    rng = np.random.default_rng(seed)
+    thr = int(round(density * 256))
+    return (rng.integers(0, 256, size=count, dtype=np.uint8) < thr).astype(np.uint8)
+
+
 def rsa(n: int, seed: int, side: float = 20.0, dmin: float = 0.8,
         batch: int = 8192, max_tries: int = 50_000_000) -> np.ndarray:
     """Random sequential adsorption of ``n`` points in [0, side)^3.

@@ -166,6 +166,17 @@ def test_validation_errors_before_any_device_work():
     assert L.smx_edm_tiled(null, 10, 3, 3, 0, 9, null, null, 0, null, null) == 1
     assert L.smx_edm_tiled(ctypes.c_void_p(256), 10, 3, 3, 0, 1, ctypes.c_void_p(256), null, 0, null, null) == 1
     assert L.smx_edm_tiled(null, 0, 3, 3, 0, 0, null, null, 0, null, null) == 0
+    # Life on the 2-simplex: n negative / past 2^24, bad map, NULL or aliased
+    # buffers, statistics without a workspace; n = 0 is a no-op
+    a, b = ctypes.c_void_p(256), ctypes.c_void_p(4352)
+    assert L.smx_simplex_life(a, b, -1, 0, null, null, 0, null) == 1
+    assert L.smx_simplex_life(a, b, (1 << 24) + 1, 0, null, null, 0, null) == 2
+    assert L.smx_simplex_life(a, b, 100, 6, null, null, 0, null) == 1
+    assert L.smx_simplex_life(null, b, 100, 0, null, null, 0, null) == 1
+    assert L.smx_simplex_life(a, a, 100, 0, null, null, 0, null) == 1
+    assert L.smx_simplex_life(a, b, 100, 0, ctypes.c_void_p(8), null, 0, null) == 1
+    assert b"workspace" in L.smx_last_error()
+    assert L.smx_simplex_life(null, null, 0, 0, null, null, 0, null) == 0
     # probe: NULL output, block count, iterations
     assert L.smx_probe_valu(null, 1, 1, null) == 1
     assert L.smx_probe_valu(ctypes.c_void_p(256), 0, 1, null) == 1
