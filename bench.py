@@ -38,7 +38,7 @@ LJ_FLOPS = 30                              # declared flops per pair (fwd + bwd)
 # rocprofv3 PMC passes (FETCH_SIZE, WRITE_SIZE, scaled by a 1 GiB copy) recorded
 # in profiles/step_lambda_hbm_traffic_pmc.md.  They describe the kernel built
 # from sources with this hash; once those change the figure is reported as null.
-AT_TRAFFIC = {"src_sha16": "ec04e7f17bdac2a6", "fetch_bytes": 0.000934e9, "write_bytes": 19.645e9,
+AT_TRAFFIC = {"src_sha16": "f442aa4dab69f827", "fetch_bytes": 0.000934e9, "write_bytes": 19.645e9,
               "valu_instructions": 42596757504}  # SQ_INSTS_VALU (wave instructions) per launch
 # single-issue FP32 vector rate: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
 VALU_ISSUE_SPEC = 256 * 4 * 16 * 2.4e9
@@ -308,7 +308,7 @@ def main():
             "quadruplets": nq, "contact_radius": QUAD_RC, "cliques": int(cnt.item()),
             "ms": t * 1e3, "quadruplets_per_s": nq / t, "maps": qd,
             "speedup_lambda_vs_bbox": (qd["bbox"]["words_ms"] + qd["bbox"]["quad_ms"]) / (t * 1e3),
-            "per_unit": "64^4 quadruplets per block; 3 KB of contact words read per block"}
+            "per_unit": "64^4 quadruplets per tile (one wave per tile, 16 tiles per wave); 3 KB of contact words read per tile"}
         del ws4
 
     # Life on the 2-simplex of cells, n = 32768, tile-contiguous 64 x 64 byte

@@ -109,11 +109,11 @@ __device__ __forceinline__ bool tile3_raw(const MapGeom &g, uint64_t &lin, int &
 // grid: every map, the bounding box included, runs on a 1-D (or 2-D) launch,
 // and the bounding box decodes its block index with divisions by nb.  The
 // from-below map is not defined for m = 4 (the host rejects it).
-template <int MAP, bool XCD>
-__device__ __forceinline__ bool tile4_raw(const MapGeom &g, uint64_t &lin, int X[4]) {
-    lin = uint64_t(blockIdx.y) * gridDim.x + blockIdx.x;
-    if (lin >= g.G) return false;
-    const uint32_t id = XCD ? xcd_remap(uint32_t(lin), uint32_t(g.G)) : uint32_t(lin);
+//
+// tile4_decode: the tile of logical block id (< G); lin gets the id (offset by
+// the cube's first id for one launch of the launch-per-cube recursion).
+template <int MAP>
+__device__ __forceinline__ bool tile4_decode(const MapGeom &g, uint32_t id, uint64_t &lin, int X[4]) {
     lin = id;
     if (MAP == MAP_BBOX) {
         const uint32_t nb = uint32_t(g.nb);
@@ -138,6 +138,14 @@ __device__ __forceinline__ bool tile4_raw(const MapGeom &g, uint64_t &lin, int X
     return false;
 }
 
+template <int MAP, bool XCD>
+__device__ __forceinline__ bool tile4_raw(const MapGeom &g, uint64_t &lin, int X[4]) {
+    lin = uint64_t(blockIdx.y) * gridDim.x + blockIdx.x;
+    if (lin >= g.G) return false;
+    const uint32_t id = XCD ? xcd_remap(uint32_t(lin), uint32_t(g.G)) : uint32_t(lin);
+    return tile4_decode<MAP>(g, id, lin, X);
+}
+
 // The map entry points used by the kernels: the raw map, then (checked builds)
 // the tile's place in the simplex.
 template <int MAP, bool XCD>
@@ -157,6 +165,16 @@ __device__ __forceinline__ bool tile3_of(const MapGeom &g, uint64_t &lin, int &X
 template <int MAP, bool XCD>
 __device__ __forceinline__ bool tile4_of(const MapGeom &g, uint64_t &lin, int X[4]) {
     bool ok = tile4_raw<MAP, XCD>(g, lin, X);
+    if (SMX_CHECKED && ok)
+        ok = smx_check(0 <= X[0] && X[0] <= X[1] && X[1] <= X[2] && X[2] <= X[3] && X[3] < g.nb, kCheckMap);
+    return ok;
+}
+
+// The tile of a given logical block id (< G), for kernels whose blocks take
+// several tiles.
+template <int MAP>
+__device__ __forceinline__ bool tile4_of_id(const MapGeom &g, uint32_t id, uint64_t &lin, int X[4]) {
+    bool ok = tile4_decode<MAP>(g, id, lin, X);
     if (SMX_CHECKED && ok)
         ok = smx_check(0 <= X[0] && X[0] <= X[1] && X[1] <= X[2] && X[2] <= X[3] && X[3] < g.nb, kCheckMap);
     return ok;

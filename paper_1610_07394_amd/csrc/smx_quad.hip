@@ -11,14 +11,14 @@
 //      decided on the FP32 squared distance fl(fma(dz,dz, fma(dy,dy, dx*dx))),
 //      d* = fl(x_j* - x_i*), below fl(rc*rc).  Column-tile-major, so the 64
 //      words of one tile pair are contiguous.
-//   2. cliques (4-simplex, one 256-thread block per tile X1 <= X2 <= X3 <= X4):
-//      the six 64-word blocks of the tile's index sets go to LDS; thread t takes
-//      p1 = t / 4 and sixteen p2, and for every contact (p1, p2) and every
-//      common neighbour p3 (bits of W13[p1] & W23[p2]) adds
-//      popcount(W14[p1] & W24[p2] & W34[p3]).  The ordering i < j < k < l within
-//      equal tiles and the bound n are already in the words.
-// Contacts are sparse, so a block does little arithmetic: the pass is bound by
-// how many blocks the map launches and by the 3 KB of words each block reads.
+//   2. cliques (4-simplex, one wave per tile X1 <= X2 <= X3 <= X4): lane p1
+//      holds words p1 of the six 64-word blocks of the tile's index sets, and
+//      for every contact (p1, p2) and every common neighbour p3 (bits of
+//      W13[p1] & W23[p2]) adds popcount(W14[p1] & W24[p2] & W34[p3]).  The
+//      ordering i < j < k < l within equal tiles and the bound n are already in
+//      the words.
+// Contacts are sparse, so a tile needs little arithmetic: the pass is bound by
+// the map evaluation per tile and by the 3 KB of words each tile reads.
 #include "smx_device.h"
 #include "smx_internal.h"
 
@@ -26,6 +26,7 @@ namespace smx {
 
 constexpr int kQuadWordThreads = 64;
 constexpr int kQuadThreads = 256;
+constexpr int kQuadTPW = 16;  // tiles per wave
 
 template <int MAP>
 __global__ __launch_bounds__(kQuadWordThreads) void contact_words_kernel(MapGeom g, const float *__restrict__ Xp,
@@ -79,65 +80,67 @@ __device__ __forceinline__ uint64_t quad_tile_volume(const int T[4], int64_t n) 
     return cnt;
 }
 
+// One wave per tile, kQuadTPW tiles per wave: the block's waves take the
+// logical block ids 4 kQuadTPW b + 4 it + w (it < kQuadTPW), so a launch of
+// G / 64 blocks carries the G tiles of the map.  (With one 256-thread block per
+// tile, dispatch and block barriers took most of the time: the clique pass ran
+// 2.9x longer on lambda4.)  Each wave evaluates the map for its own id (the
+// decode is uniform across the wave), loads the six 64-word blocks of its
+// tile's index sets (lane p holds word p of each), keeps its own three in
+// registers and shares the other three through its own 3 KB of LDS, and lane
+// p1 = p walks its 64 p2 bits.
 template <int MAP, bool STATS>
 __global__ __launch_bounds__(kQuadThreads) void quad_kernel(MapGeom g, const uint64_t *__restrict__ W, int64_t npad,
                                                            int64_t n, unsigned long long *cslots,
                                                            unsigned long long *sslots) {
     // pair sets s = (a, b): 0 (0,1), 1 (0,2), 2 (0,3), 3 (1,2), 4 (1,3), 5 (2,3)
-    __shared__ uint64_t A[6][kQuadTile];
-    __shared__ unsigned long long red[kQuadThreads / kWave];
-    __shared__ int tileS[5];
-    __shared__ uint64_t linS;
-    const int t = threadIdx.x;
-    // A block does little work, so its map evaluation shows: the first wave
-    // evaluates it once for the block.  No XCD renumbering: the 4-simplex maps
-    // leave their filtered blocks in long runs (the tail of each lambda4 node),
-    // which contiguous per-XCD ranges would hand to a few XCDs only.
-    if (t < kWave) {
-        uint64_t l;
-        int Tw[4];
-        const bool ok = tile4_of<MAP, false>(g, l, Tw);
-        if (t == 0) {
-            tileS[0] = Tw[0];
-            tileS[1] = Tw[1];
-            tileS[2] = Tw[2];
-            tileS[3] = Tw[3];
-            tileS[4] = ok;
-            linS = l;
-        }
-    }
-    __syncthreads();
-    if (!tileS[4]) return;
-    const int T[4] = {tileS[0], tileS[1], tileS[2], tileS[3]};
-    const uint64_t lin = linS;
-    const int64_t T0 = T[0], T1 = T[1], T2 = T[2], T3 = T[3];
-    for (int e = t; e < 6 * kQuadTile; e += kQuadThreads) {
-        const int s = e >> 6, p = e & (kQuadTile - 1);
-        const int64_t ra = s < 3 ? T0 : (s < 5 ? T1 : T2);
-        const int64_t cb = s == 0 ? T1 : (s == 1 || s == 3) ? T2 : T3;
-        A[s][p] = W[cb * npad + ra * kQuadTile + p];
-    }
-    __syncthreads();
-    const int p1 = t >> 2, p2b = (t & 3) << 4;
-    const uint64_t a02 = A[1][p1], a03 = A[2][p1];
-    uint32_t bits = uint32_t(A[0][p1] >> p2b) & 0xFFFFu;
+    __shared__ uint64_t A[kQuadThreads / kWave][6][kQuadTile];
+    const int w = threadIdx.x / kWave, p = threadIdx.x & (kWave - 1);
+    const uint64_t b = uint64_t(blockIdx.y) * gridDim.x + blockIdx.x;
+    uint64_t (*Aw)[kQuadTile] = A[w];
     uint32_t cnt = 0;
-    while (bits != 0) {
-        const int p2 = p2b + __builtin_ctz(bits);
-        bits &= bits - 1u;
-        uint64_t m3 = a02 & A[3][p2];
-        const uint64_t w = a03 & A[4][p2];
-        while (m3 != 0) {
-            const int p3 = __builtin_ctzll(m3);
-            m3 &= m3 - 1;
-            cnt += uint32_t(__builtin_popcountll(w & A[5][p3]));
+    uint64_t lin0 = 0;
+    for (int it = 0; it < kQuadTPW; ++it) {
+        const uint64_t id = (b * kQuadTPW + uint64_t(it)) * (kQuadThreads / kWave) + uint64_t(w);
+        if (id >= g.G) break;
+        uint64_t lin;
+        int T[4];
+        if (!tile4_of_id<MAP>(g, uint32_t(id), lin, T)) continue;
+        if (it == 0) lin0 = lin;
+        const int64_t T0 = T[0], T1 = T[1], T2 = T[2], T3 = T[3];
+        uint64_t a[6];
+#pragma unroll
+        for (int s = 0; s < 6; ++s) {
+            const int64_t ra = s < 3 ? T0 : (s < 5 ? T1 : T2);
+            const int64_t cb = s == 0 ? T1 : (s == 1 || s == 3) ? T2 : T3;
+            a[s] = W[cb * npad + ra * kQuadTile + p];
+        }
+        // the previous tile's reads of this wave's LDS are done before it is
+        // overwritten, and the writes land before other lanes read them
+        __builtin_amdgcn_wave_barrier();
+#pragma unroll
+        for (int s = 3; s < 6; ++s) Aw[s][p] = a[s];
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        uint64_t bits = a[0];
+        while (bits != 0) {
+            const int p2 = __builtin_ctzll(bits);
+            bits &= bits - 1;
+            uint64_t m3 = a[1] & Aw[3][p2];
+            const uint64_t wv = a[2] & Aw[4][p2];
+            while (m3 != 0) {
+                const int p3 = __builtin_ctzll(m3);
+                m3 &= m3 - 1;
+                cnt += uint32_t(__builtin_popcountll(wv & Aw[5][p3]));
+            }
+        }
+        if (STATS) {
+            if (p == 0) stats_add(sslots, lin, quad_tile_volume(T, n), 0);
         }
     }
-    const unsigned long long c = block_sum<unsigned long long, kQuadThreads>(cnt, red);
-    if (t == 0) {
-        if (c != 0) atomicAdd(cslots + (lin % kSlots) * kSlotStride, c);
-        if (STATS) stats_add(sslots, lin, quad_tile_volume(T, n), 0);
-    }
+    const unsigned c = wave_sum(cnt);
+    if (p == 0 && c != 0) atomicAdd(cslots + (lin0 % kSlots) * kSlotStride, (unsigned long long)c);
 }
 
 __global__ void count_finalize_kernel(const unsigned long long *slots, int64_t *out) {
@@ -164,7 +167,8 @@ int launch_quad(const MapGeom &g, const uint64_t *W, int64_t npad, int64_t n, un
     prof_begin(K_QUAD, s);
     for_each_launch(g, [&](auto M, const MapGeom &gg) {
         constexpr int MAPK = decltype(M)::value;
-        const dim3 grid = grid_for(gg.G, kQuadThreads);
+        const uint64_t per_block = uint64_t(kQuadTPW) * (kQuadThreads / kWave);
+        const dim3 grid = grid_for((gg.G + per_block - 1) / per_block, kQuadThreads);
         if (sslots)
             hipLaunchKernelGGL((quad_kernel<MAPK, true>), grid, dim3(kQuadThreads), 0, s, gg, W, npad, n, cslots,
                                sslots);
