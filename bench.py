@@ -308,7 +308,7 @@ def main():
             "quadruplets": nq, "contact_radius": QUAD_RC, "cliques": int(cnt.item()),
             "ms": t * 1e3, "quadruplets_per_s": nq / t, "maps": qd,
             "speedup_lambda_vs_bbox": (qd["bbox"]["words_ms"] + qd["bbox"]["quad_ms"]) / (t * 1e3),
-            "per_unit": "64^4 quadruplets per tile (one wave per tile, 16 tiles per wave); 3 KB of contact words read per tile"}
+            "per_unit": "64^4 quadruplets per tile (map decoded one id per lane, tiles counted one per wave at a time); 3 KB of contact words read per mapped tile"}
         del ws4
 
     # Life on the 2-simplex of cells, n = 32768, tile-contiguous 64 x 64 byte

@@ -311,8 +311,8 @@ int smx_triplet_packed_tiled(const float *d_X, int64_t n, int64_t ldx, double nu
  *            64 X + p with columns 64 Y .. 64 Y + 63 (upper tiles X <= Y only).
  *   d_stats  int64[4] or NULL: [0] quadruplets covered (C(n, 4) when every tile
  *            is visited once), [1] 0, [2] mapped 4-simplex blocks, [3] 4-simplex
- *            blocks of the parallel space (logical blocks: the clique pass runs
- *            each on one wave, 64 per 256-thread hardware block).
+ *            blocks of the parallel space (logical blocks: the clique pass
+ *            decodes them one per lane, 256 per hardware block).
  * Asynchronous on `stream`; the result is exact, so every map returns the same
  * count. */
 int smx_quad_contacts(const float *d_X, int64_t n, int64_t ldx, double rc, int map, int64_t *d_count,

@@ -11,14 +11,14 @@
 //      decided on the FP32 squared distance fl(fma(dz,dz, fma(dy,dy, dx*dx))),
 //      d* = fl(x_j* - x_i*), below fl(rc*rc).  Column-tile-major, so the 64
 //      words of one tile pair are contiguous.
-//   2. cliques (4-simplex, one wave per tile X1 <= X2 <= X3 <= X4): lane p1
-//      holds words p1 of the six 64-word blocks of the tile's index sets, and
-//      for every contact (p1, p2) and every common neighbour p3 (bits of
-//      W13[p1] & W23[p2]) adds popcount(W14[p1] & W24[p2] & W34[p3]).  The
-//      ordering i < j < k < l within equal tiles and the bound n are already in
-//      the words.
+//   2. cliques (4-simplex, tiles X1 <= X2 <= X3 <= X4, each counted by one
+//      wave): lane p1 holds words p1 of the six 64-word blocks of the tile's
+//      index sets, and for every contact (p1, p2) and every common neighbour p3
+//      (bits of W13[p1] & W23[p2]) adds popcount(W14[p1] & W24[p2] & W34[p3]).
+//      The ordering i < j < k < l within equal tiles and the bound n are
+//      already in the words.
 // Contacts are sparse, so a tile needs little arithmetic: the pass is bound by
-// the map evaluation per tile and by the 3 KB of words each tile reads.
+// the 3 KB of words each mapped tile reads from L2.
 #include "smx_device.h"
 #include "smx_internal.h"
 
@@ -26,7 +26,6 @@ namespace smx {
 
 constexpr int kQuadWordThreads = 64;
 constexpr int kQuadThreads = 256;
-constexpr int kQuadTPW = 16;  // tiles per wave
 
 template <int MAP>
 __global__ __launch_bounds__(kQuadWordThreads) void contact_words_kernel(MapGeom g, const float *__restrict__ Xp,
@@ -80,67 +79,100 @@ __device__ __forceinline__ uint64_t quad_tile_volume(const int T[4], int64_t n) 
     return cnt;
 }
 
-// One wave per tile, kQuadTPW tiles per wave: the block's waves take the
-// logical block ids 4 kQuadTPW b + 4 it + w (it < kQuadTPW), so a launch of
-// G / 64 blocks carries the G tiles of the map.  (With one 256-thread block per
-// tile, dispatch and block barriers took most of the time: the clique pass ran
-// 2.9x longer on lambda4.)  Each wave evaluates the map for its own id (the
-// decode is uniform across the wave), loads the six 64-word blocks of its
-// tile's index sets (lane p holds word p of each), keeps its own three in
-// registers and shares the other three through its own 3 KB of LDS, and lane
-// p1 = p walks its 64 p2 bits.
+// One wave per 64 logical block ids, one tile at a time.  Lane q evaluates the
+// map for id 64 (4 b + w) + q, so a wave decodes its 64 ids in one pass and an
+// id outside the simplex costs one lane of that pass; the wave then walks the
+// mapped tiles (a ballot of the lanes' results) with each tile's coordinates
+// read from the lane that decoded it, loading the next tile's words while it
+// counts the current one.  Per tile, lane p holds word p of the six 64-word
+// blocks of the index sets, keeps its own three in registers, shares the other
+// three through the wave's 1.5 KB of LDS, and walks its 64 p2 bits.  A launch
+// has G / 256 hardware blocks.
 template <int MAP, bool STATS>
 __global__ __launch_bounds__(kQuadThreads) void quad_kernel(MapGeom g, const uint64_t *__restrict__ W, int64_t npad,
                                                            int64_t n, unsigned long long *cslots,
                                                            unsigned long long *sslots) {
-    // pair sets s = (a, b): 0 (0,1), 1 (0,2), 2 (0,3), 3 (1,2), 4 (1,3), 5 (2,3)
-    __shared__ uint64_t A[kQuadThreads / kWave][6][kQuadTile];
+    // pair sets s = (a, b): 0 (0,1), 1 (0,2), 2 (0,3), 3 (1,2), 4 (1,3), 5 (2,3);
+    // sets 3..5 are read across lanes
+    __shared__ uint64_t A[kQuadThreads / kWave][3][kQuadTile];
     const int w = threadIdx.x / kWave, p = threadIdx.x & (kWave - 1);
     const uint64_t b = uint64_t(blockIdx.y) * gridDim.x + blockIdx.x;
+    const uint64_t base = (b * (kQuadThreads / kWave) + uint64_t(w)) * kWave;
     uint64_t (*Aw)[kQuadTile] = A[w];
-    uint32_t cnt = 0;
-    uint64_t lin0 = 0;
-    for (int it = 0; it < kQuadTPW; ++it) {
-        const uint64_t id = (b * kQuadTPW + uint64_t(it)) * (kQuadThreads / kWave) + uint64_t(w);
-        if (id >= g.G) break;
-        uint64_t lin;
-        int T[4];
-        if (!tile4_of_id<MAP>(g, uint32_t(id), lin, T)) continue;
-        if (it == 0) lin0 = lin;
-        const int64_t T0 = T[0], T1 = T[1], T2 = T[2], T3 = T[3];
-        uint64_t a[6];
+
+    uint64_t mylin = 0;
+    int Tq[4] = {0, 0, 0, 0};
+    bool ok = false;
+    if (base + uint64_t(p) < g.G) ok = tile4_of_id<MAP>(g, uint32_t(base + uint64_t(p)), mylin, Tq);
+    uint64_t mask = __ballot(ok);
+
+    // coordinates of the tile decoded by lane q (q uniform), and its words
+    auto coords = [&](int q, int T[4]) {
+#pragma unroll
+        for (int d = 0; d < 4; ++d) T[d] = __builtin_amdgcn_readlane(Tq[d], q);
+    };
+    auto load = [&](const int T[4], uint64_t a[6]) {
 #pragma unroll
         for (int s = 0; s < 6; ++s) {
-            const int64_t ra = s < 3 ? T0 : (s < 5 ? T1 : T2);
-            const int64_t cb = s == 0 ? T1 : (s == 1 || s == 3) ? T2 : T3;
+            const int64_t ra = s < 3 ? T[0] : (s < 5 ? T[1] : T[2]);
+            const int64_t cb = s == 0 ? T[1] : (s == 1 || s == 3) ? T[2] : T[3];
             a[s] = W[cb * npad + ra * kQuadTile + p];
         }
-        // the previous tile's reads of this wave's LDS are done before it is
-        // overwritten, and the writes land before other lanes read them
-        __builtin_amdgcn_wave_barrier();
-#pragma unroll
-        for (int s = 3; s < 6; ++s) Aw[s][p] = a[s];
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        uint64_t bits = a[0];
-        while (bits != 0) {
-            const int p2 = __builtin_ctzll(bits);
-            bits &= bits - 1;
-            uint64_t m3 = a[1] & Aw[3][p2];
-            const uint64_t wv = a[2] & Aw[4][p2];
-            while (m3 != 0) {
-                const int p3 = __builtin_ctzll(m3);
-                m3 &= m3 - 1;
-                cnt += uint32_t(__builtin_popcountll(wv & Aw[5][p3]));
+    };
+
+    uint32_t cnt = 0;
+    if (mask != 0) {
+        int q = __builtin_ctzll(mask);
+        mask &= mask - 1;
+        int T[4];
+        uint64_t a[6];
+        coords(q, T);
+        load(T, a);
+        while (true) {
+            const bool more = mask != 0;
+            int qn = 0, Tn[4] = {0, 0, 0, 0};
+            uint64_t an[6] = {0, 0, 0, 0, 0, 0};
+            if (more) {
+                qn = __builtin_ctzll(mask);
+                mask &= mask - 1;
+                coords(qn, Tn);
+                load(Tn, an);
             }
-        }
-        if (STATS) {
-            if (p == 0) stats_add(sslots, lin, quad_tile_volume(T, n), 0);
+            // the previous tile's reads of this wave's LDS are done before it is
+            // overwritten, and the writes land before other lanes read them
+            __builtin_amdgcn_wave_barrier();
+#pragma unroll
+            for (int s = 0; s < 3; ++s) Aw[s][p] = a[3 + s];
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            uint64_t bits = a[0];
+            while (bits != 0) {
+                const int p2 = __builtin_ctzll(bits);
+                bits &= bits - 1;
+                uint64_t m3 = a[1] & Aw[0][p2];
+                const uint64_t wv = a[2] & Aw[1][p2];
+                while (m3 != 0) {
+                    const int p3 = __builtin_ctzll(m3);
+                    m3 &= m3 - 1;
+                    cnt += uint32_t(__builtin_popcountll(wv & Aw[2][p3]));
+                }
+            }
+            if (STATS && p == 0) {
+                const uint64_t lin = uint64_t(__builtin_amdgcn_readlane(uint32_t(mylin), q)) |
+                                     (uint64_t(__builtin_amdgcn_readlane(uint32_t(mylin >> 32), q)) << 32);
+                stats_add(sslots, lin, quad_tile_volume(T, n), 0);
+            }
+            if (!more) break;
+            q = qn;
+#pragma unroll
+            for (int d = 0; d < 4; ++d) T[d] = Tn[d];
+#pragma unroll
+            for (int s = 0; s < 6; ++s) a[s] = an[s];
         }
     }
     const unsigned c = wave_sum(cnt);
-    if (p == 0 && c != 0) atomicAdd(cslots + (lin0 % kSlots) * kSlotStride, (unsigned long long)c);
+    if (p == 0 && c != 0) atomicAdd(cslots + (base / kWave % kSlots) * kSlotStride, (unsigned long long)c);
 }
 
 __global__ void count_finalize_kernel(const unsigned long long *slots, int64_t *out) {
@@ -167,7 +199,7 @@ int launch_quad(const MapGeom &g, const uint64_t *W, int64_t npad, int64_t n, un
     prof_begin(K_QUAD, s);
     for_each_launch(g, [&](auto M, const MapGeom &gg) {
         constexpr int MAPK = decltype(M)::value;
-        const uint64_t per_block = uint64_t(kQuadTPW) * (kQuadThreads / kWave);
+        const uint64_t per_block = kQuadThreads;  // one id per thread
         const dim3 grid = grid_for((gg.G + per_block - 1) / per_block, kQuadThreads);
         if (sslots)
             hipLaunchKernelGGL((quad_kernel<MAPK, true>), grid, dim3(kQuadThreads), 0, s, gg, W, npad, n, cslots,
