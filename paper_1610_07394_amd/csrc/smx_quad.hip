@@ -18,7 +18,8 @@
 //      The ordering i < j < k < l within equal tiles and the bound n are
 //      already in the words.
 // Contacts are sparse, so a tile needs little arithmetic: the pass is bound by
-// the 3 KB of words each mapped tile reads from L2.
+// each wave's chain of per-tile word loads (3 KB per tile, from L2) and LDS
+// exchange.
 #include "smx_device.h"
 #include "smx_internal.h"
 
