@@ -90,6 +90,22 @@ def test_life_generations_vs_oracle(kind, n):
         cur, nxt = nxt, cur
 
 
+@pytest.mark.parametrize("kind", ["lambda", "linear"])
+def test_life_mid_size_ragged(kind):
+    """n = 1000 (16 tiles per side, the last 40 cells wide): three generations
+    of a denser start, bit for bit."""
+    n = 1000
+    A = synth.bits(n, seed=11, density=0.45)
+    cur = torch.from_numpy(to_tiled(A, n)).cuda()
+    nxt = torch.empty_like(cur)
+    ref = A
+    for gen in range(3):
+        smx.simplex_life(cur, n, kind, out=nxt)
+        ref = oracle.life_step(ref)
+        assert np.array_equal(from_tiled(nxt.cpu().numpy(), n), ref), f"generation {gen + 1} differs"
+        cur, nxt = nxt, cur
+
+
 @pytest.mark.parametrize("kind", ["lambda", "bbox", "recursive"])
 def test_life_stats(kind):
     n = 517

@@ -81,3 +81,23 @@ def test_contacts_full_size_n8192():
         print(f"  {kind}: {int(c.item())}", flush=True)
         assert int(c.item()) == ref
         assert int(s[0]) == math.comb(8192, 4) and int(s[2]) == math.comb(128 + 3, 4)
+
+
+def test_contacts_max_size_n16384():
+    """The largest n the entry point takes (nb = 256 tiles per dimension), a
+    uniform cloud at the same contact degree as the n = 8192 set; the bounding
+    box's 256^4 ids exceed the launch limit and are refused."""
+    n = 16384
+    X = synth.uniform(n, 3, seed=16) * np.float32(20.0 * 2 ** (1 / 3))
+    Xt = _gpu(X)
+    ref = oracle.quad_contacts(X, 2.0)
+    print(f"  oracle: {ref} 4-cliques", flush=True)
+    assert ref > 0
+    for kind in ["lambda", "linear", "recursive"]:
+        c, s = smx.quad_contacts(Xt, 2.0, kind, stats=True)
+        s = s.cpu().numpy()
+        print(f"  {kind}: {int(c.item())}", flush=True)
+        assert int(c.item()) == ref
+        assert int(s[0]) == math.comb(n, 4) and int(s[2]) == math.comb(256 + 3, 4)
+    with pytest.raises(Exception):
+        smx.quad_contacts(Xt, 2.0, "bbox")
