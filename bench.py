@@ -38,7 +38,7 @@ LJ_FLOPS = 30                              # declared flops per pair (fwd + bwd)
 # rocprofv3 PMC passes (FETCH_SIZE, WRITE_SIZE, scaled by a 1 GiB copy) recorded
 # in profiles/step_lambda_hbm_traffic_pmc.md.  They describe the kernel built
 # from sources with this hash; once those change the figure is reported as null.
-AT_TRAFFIC = {"src_sha16": "f442aa4dab69f827", "fetch_bytes": 0.000934e9, "write_bytes": 19.645e9,
+AT_TRAFFIC = {"src_sha16": "0932782567cbd740", "fetch_bytes": 0.000934e9, "write_bytes": 19.645e9,
               "valu_instructions": 42596757504}  # SQ_INSTS_VALU (wave instructions) per launch
 # single-issue FP32 vector rate: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
 VALU_ISSUE_SPEC = 256 * 4 * 16 * 2.4e9
@@ -417,6 +417,17 @@ def main():
                     ms, c = smx.profile_read(f"map{m}")
                     smx.profile_enable(False)
                     mo[f"{what}{m}_{kind}_n{n}_rho{rho}_ms"] = ms / c
+                # the map alone, one lane per logical block id (no block per tile)
+                nb = n // rho
+                smx.simplex_decode(m, nb, kind)
+                torch.cuda.synchronize()
+                smx.profile_enable(True)
+                smx.profile_reset()
+                for _ in range(3):
+                    smx.simplex_decode(m, nb, kind)
+                ms, c = smx.profile_read("decode")
+                smx.profile_enable(False)
+                mo[f"decode{m}_{kind}_nb{nb}_ms"] = ms / c
         compare["map_only"] = mo
 
     # ---- CPU baseline: the FP64 oracle on a bounded sample, host cores

@@ -196,6 +196,21 @@ int smx_simplex_map3(int64_t n, int rho, int map, int strict, int32_t *d_tiles,
 int smx_simplex_map4(int64_t n, int rho, int map, int strict, int32_t *d_tiles,
                      int64_t *d_stats, void *d_ws, size_t ws_bytes, void *stream);
 
+/* The map alone, one lane per logical block id (Sec. III: the cost of evaluating
+ * a map): every thread decodes 16 ids of the parallel space of map `map` over
+ * the m-simplex of nb x ... x nb tiles (no element work, no block per tile), so
+ * the time is the map's arithmetic per id plus the ids a map wastes, free of
+ * block dispatch.  m = 2, 3 or 4; nb >= 0 (0: no work); LAMBDA_BELOW is not
+ * defined for m = 4 (SMX_EUNSUPPORTED).
+ *   d_stats  int64[4] device, required: [0] mapped ids (|T_m| = C(nb+m-1, m) for
+ *            every map), [1] wrapping sum of SplitMix64 of the mapped tiles'
+ *            colex ranks (X + C(Y+1, 2) + C(Z+2, 3) + C(W+3, 4), so the sum over
+ *            a bijection onto T_m is that of the range [0, |T_m|)), [2] hardware
+ *            blocks that mapped an id, [3] logical ids decoded (|Pi|).
+ *   d_ws     >= smx_workspace_bytes(0, ...) bytes of device memory (the slots).
+ * Asynchronous on `stream`. */
+int smx_simplex_decode(int m, int64_t nb, int map, int64_t *d_stats, void *d_ws, size_t ws_bytes, void *stream);
+
 /* Parallel space only (paper Sec. I and III: the cost of a map is the map plus
  * the blocks it launches).  Launches the parallel space of `map` for m in
  * {2, 3, 4}, n elements per dimension and tile edge rho (power of two, <= 1024
@@ -363,7 +378,7 @@ int smx_scale_grad(const float *d_G, int64_t n, const double *d_gradE, float *d_
  * returns the summed duration (ms) and launch count of kernel `kernel_id`
  * (0 map2, 1 map3, 2 edm diff, 3 edm gram, 4 gram prep, 5 triplet energy,
  * 6 triplet grad, 7 lj, 8 finalize, 9 triplet packed, 10 map4, 11 contact words,
- * 12 quad contacts, 13 triplet packed tiled, 14 life) since the last reset; it
+ * 12 quad contacts, 13 triplet packed tiled, 14 life, 15 decode) since the last reset; it
  * returns SMX_EINVAL
  * for an unknown id.  smx_profile_reset clears the totals.  Host only. */
 int smx_profile_enable(int on);

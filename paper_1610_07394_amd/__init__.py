@@ -16,7 +16,7 @@ import torch
 
 __all__ = [
     "MAPS", "PRECS", "SmxError", "Pot", "lib", "volume", "parallel_blocks", "map_tiles_host", "map_blocks_host",
-    "workspace_bytes", "simplex_map2", "simplex_map3", "simplex_map4", "simplex_count", "triplet_packed", "triplet_packed_tiled", "triplet_tiled_len", "edm_tiled", "edm_tiled_len", "life_len", "simplex_life", "quad_contacts", "edm_packed", "triplet_energy",
+    "workspace_bytes", "simplex_map2", "simplex_map3", "simplex_map4", "simplex_count", "triplet_packed", "triplet_packed_tiled", "triplet_tiled_len", "edm_tiled", "edm_tiled_len", "life_len", "simplex_life", "simplex_decode", "quad_contacts", "edm_packed", "triplet_energy",
     "triplet_energy_grad", "triplet_energy_backward", "TripletEnergy", "profile_enable",
     "profile_reset", "profile_read", "KERNELS", "select_library", "check_flags",
 ]
@@ -30,7 +30,7 @@ MAPS = {"lambda": 0, "bbox": 1, "linear": 2, "lambda_below": 3, "recursive": 4, 
 PRECS = {"fp32": 0, "bf16": 1, "split_bf16": 2}
 KERNELS = {"map2": 0, "map3": 1, "edm_diff": 2, "edm_gram": 3, "gram_prep": 4,
            "triplet_energy": 5, "triplet_grad": 6, "lj": 7, "finalize": 8, "triplet_packed": 9, "map4": 10,
-           "quad_words": 11, "quad": 12, "triplet_tiled": 13, "life": 14}
+           "quad_words": 11, "quad": 12, "triplet_tiled": 13, "life": 14, "decode": 15}
 
 _i32, _i64, _sz, _vp, _dbl = ctypes.c_int, ctypes.c_int64, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_double
 
@@ -83,6 +83,7 @@ def lib():
         L.smx_triplet_packed.argtypes = [_vp, _i64, _i64, _dbl, _i32, _vp, _vp, _sz, _vp, _vp]
         L.smx_edm_tiled.argtypes = [_vp, _i64, _i64, _i64, _i32, _i32, _vp, _vp, _sz, _vp, _vp]
         L.smx_simplex_life.argtypes = [_vp, _vp, _i64, _i32, _vp, _vp, _sz, _vp]
+        L.smx_simplex_decode.argtypes = [_i32, _i64, _i32, _vp, _vp, _sz, _vp]
         L.smx_triplet_packed_tiled.argtypes = [_vp, _i64, _i64, _dbl, _i32, _vp, _vp, _sz, _vp, _vp]
         L.smx_quad_contacts.argtypes = [_vp, _i64, _i64, _dbl, _i32, _vp, _vp, _sz, _vp, _vp]
         L.smx_check_flags.argtypes = [ctypes.POINTER(ctypes.c_uint32), _i32]
@@ -330,6 +331,17 @@ def triplet_packed_tiled(X: torch.Tensor, nu: float = 1.0, map="lambda", stats=F
     _check(lib().smx_triplet_packed_tiled(xp, n, ldx, float(nu), _map(map), _ptr(E), _ptr(ws),
                                           0 if ws is None else ws.numel(), _ptr(s), _stream()))
     return (E, s) if stats else E
+
+
+def simplex_decode(m: int, nb: int, map="lambda", ws=None, out=None):
+    """Decode every logical block id of map `map` over the m-simplex of nb tiles
+    per dimension, one per lane; int64 [4] stats (see smx_simplex_decode)."""
+    dev = torch.device("cuda", torch.cuda.current_device())
+    st = out if out is not None else torch.zeros(4, dtype=torch.int64, device=dev)
+    if ws is None:
+        ws = _ws(workspace_bytes(0, 1), dev)
+    _check(lib().smx_simplex_decode(m, nb, _map(map), _ptr(st), _ptr(ws), ws.numel(), _stream()))
+    return st
 
 
 def life_len(n: int) -> int:

@@ -380,6 +380,23 @@ int smx_simplex_count(int m, int64_t n, int rho, int map, int strict, int64_t *d
     return launch_stats_finalize(slots, g.G, d_stats, S(stream));
 }
 
+int smx_simplex_decode(int m, int64_t nb, int map, int64_t *d_stats, void *d_ws, size_t ws_bytes, void *stream) {
+    if (m < 2 || m > 4) return fail(SMX_EINVAL, "m must be 2, 3 or 4 (got %d)", m);
+    if (nb < 0) return fail(SMX_EINVAL, "nb must be >= 0 (got %lld)", (long long)nb);
+    if (nb > kMaxN) return fail(SMX_EOVERFLOW, "nb = %lld exceeds 2^31 - 1", (long long)nb);
+    if (map < 0 || map > MAP_REC_LAUNCH) return fail(SMX_EINVAL, "unknown map %d", map);
+    if (d_stats == nullptr) return fail(SMX_EINVAL, "stats must not be NULL");
+    if (d_ws == nullptr || ws_bytes < kSlotBytes)
+        return fail(SMX_EINVAL, "a workspace of %zu bytes is required", kSlotBytes);
+    MapGeom g{};
+    if (nb > 0 && !make_geom(m, nb, map, g)) return g_status;
+    unsigned long long *slots = reinterpret_cast<unsigned long long *>(d_ws);
+    int rc;
+    if ((rc = launch_fill_u64(reinterpret_cast<uint64_t *>(slots), kSlotBytes / 8, S(stream)))) return rc;
+    if (nb > 0 && (rc = launch_decode(m, g, slots, S(stream)))) return rc;
+    return launch_stats_finalize(slots, g.G, d_stats, S(stream));
+}
+
 static int edm_run(bool tiled, const float *d_X, int64_t n, int64_t d, int64_t ldx, int map, int prec, float *d_D,
                    void *d_ws, size_t ws_bytes, int64_t *d_stats, void *stream) {
     if (n < 0) return fail(SMX_EINVAL, "n must be >= 0");

@@ -53,6 +53,51 @@ __device__ __forceinline__ bool launch_tail(const MapGeom &g) {
     return MAP != MAP_BBOX && launch_index() >= g.G;
 }
 
+// tile2_decode / tile3_decode: the tile of a given logical block id (< G), for
+// kernels that decode ids themselves; the bounding box's id is the row-major
+// rank of its grid position (X fastest).
+template <int MAP>
+__device__ __forceinline__ bool tile2_decode(const MapGeom &g, uint32_t id, uint64_t &lin, int &X, int &Y) {
+    lin = id;
+    if (MAP == MAP_BBOX) {
+        const uint32_t nb = uint32_t(g.nb), q = id / nb;
+        X = int(id - q * nb);
+        Y = int(q);
+        return X <= Y;
+    }
+    if (MAP == MAP_LAMBDA) return lambda2(id, g.lg, g.nb, X, Y);
+    if (MAP == MAP_BELOW) return below2(id, uint32_t(g.nb), X, Y);
+    if (MAP == MAP_REC) return rec2(id, g.lg, g.nb, uint32_t(g.G), X, Y);
+    if (MAP == MAP_CUBE) {
+        lin = g.off + id;
+        return cube2(id, g, X, Y);
+    }
+    linear2(id, X, Y);
+    return true;
+}
+
+template <int MAP>
+__device__ __forceinline__ bool tile3_decode(const MapGeom &g, uint32_t id, uint64_t &lin, int &X, int &Y,
+                                             int &Z) {
+    lin = id;
+    if (MAP == MAP_BBOX) {
+        const uint32_t nb = uint32_t(g.nb), q = id / nb, q2 = q / nb;
+        X = int(id - q * nb);
+        Y = int(q - q2 * nb);
+        Z = int(q2);
+        return X <= Y && Y <= Z;
+    }
+    if (MAP == MAP_LAMBDA) return lambda3(id, g.lg, g.nb, g.main, X, Y, Z);
+    if (MAP == MAP_BELOW) return below3(id, uint32_t(g.nb), X, Y, Z);
+    if (MAP == MAP_REC) return rec3(id, g.lg, g.nb, uint32_t(g.G), X, Y, Z);
+    if (MAP == MAP_CUBE) {
+        lin = g.off + id;
+        return cube3(id, g, X, Y, Z);
+    }
+    linear3(id, X, Y, Z);
+    return true;
+}
+
 // Tile of this block under map MAP.  Returns false for a filtered block (and
 // for the tail of a 2-D launch, where lin >= G).  `lin` receives the logical
 // block index (the dump position).  XCD: renumber the dispatch order so that
@@ -69,16 +114,7 @@ __device__ __forceinline__ bool tile2_raw(const MapGeom &g, uint64_t &lin, int &
     lin = uint64_t(blockIdx.y) * gridDim.x + blockIdx.x;
     if (lin >= g.G) return false;
     const uint32_t id = XCD ? xcd_remap(uint32_t(lin), uint32_t(g.G)) : uint32_t(lin);
-    lin = id;
-    if (MAP == MAP_LAMBDA) return lambda2(id, g.lg, g.nb, X, Y);
-    if (MAP == MAP_BELOW) return below2(id, uint32_t(g.nb), X, Y);
-    if (MAP == MAP_REC) return rec2(id, g.lg, g.nb, uint32_t(g.G), X, Y);
-    if (MAP == MAP_CUBE) {
-        lin = g.off + id;
-        return cube2(id, g, X, Y);
-    }
-    linear2(id, X, Y);
-    return true;
+    return tile2_decode<MAP>(g, id, lin, X, Y);
 }
 
 template <int MAP, bool XCD>
@@ -93,16 +129,7 @@ __device__ __forceinline__ bool tile3_raw(const MapGeom &g, uint64_t &lin, int &
     lin = uint64_t(blockIdx.y) * gridDim.x + blockIdx.x;
     if (lin >= g.G) return false;
     const uint32_t id = XCD ? xcd_remap(uint32_t(lin), uint32_t(g.G)) : uint32_t(lin);
-    lin = id;
-    if (MAP == MAP_LAMBDA) return lambda3(id, g.lg, g.nb, g.main, X, Y, Z);
-    if (MAP == MAP_BELOW) return below3(id, uint32_t(g.nb), X, Y, Z);
-    if (MAP == MAP_REC) return rec3(id, g.lg, g.nb, uint32_t(g.G), X, Y, Z);
-    if (MAP == MAP_CUBE) {
-        lin = g.off + id;
-        return cube3(id, g, X, Y, Z);
-    }
-    linear3(id, X, Y, Z);
-    return true;
+    return tile3_decode<MAP>(g, id, lin, X, Y, Z);
 }
 
 // 4-simplex tiles (X[0] <= X[1] <= X[2] <= X[3]).  There is no 4-D hardware
@@ -172,6 +199,20 @@ __device__ __forceinline__ bool tile4_of(const MapGeom &g, uint64_t &lin, int X[
 
 // The tile of a given logical block id (< G), for kernels whose blocks take
 // several tiles.
+template <int MAP>
+__device__ __forceinline__ bool tile2_of_id(const MapGeom &g, uint32_t id, uint64_t &lin, int &X, int &Y) {
+    bool ok = tile2_decode<MAP>(g, id, lin, X, Y);
+    if (SMX_CHECKED && ok) ok = smx_check(0 <= X && X <= Y && Y < g.nb, kCheckMap);
+    return ok;
+}
+
+template <int MAP>
+__device__ __forceinline__ bool tile3_of_id(const MapGeom &g, uint32_t id, uint64_t &lin, int &X, int &Y, int &Z) {
+    bool ok = tile3_decode<MAP>(g, id, lin, X, Y, Z);
+    if (SMX_CHECKED && ok) ok = smx_check(0 <= X && X <= Y && Y <= Z && Z < g.nb, kCheckMap);
+    return ok;
+}
+
 template <int MAP>
 __device__ __forceinline__ bool tile4_of_id(const MapGeom &g, uint32_t id, uint64_t &lin, int X[4]) {
     bool ok = tile4_decode<MAP>(g, id, lin, X);

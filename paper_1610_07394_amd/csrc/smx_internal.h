@@ -44,7 +44,7 @@ unsigned check_flags_life(bool clear);
 enum KernelId {
     K_MAP2 = 0, K_MAP3 = 1, K_EDM_DIFF = 2, K_EDM_GRAM = 3, K_GRAM_PREP = 4,
     K_TRIP_ENERGY = 5, K_TRIP_GRAD = 6, K_LJ = 7, K_FINALIZE = 8, K_TRIP_PACKED = 9, K_MAP4 = 10,
-    K_QUAD_WORDS = 11, K_QUAD = 12, K_TRIP_TILED = 13, K_LIFE = 14, K_COUNT = 15
+    K_QUAD_WORDS = 11, K_QUAD = 12, K_TRIP_TILED = 13, K_LIFE = 14, K_DECODE = 15, K_COUNT = 16
 };
 void prof_begin(int kid, hipStream_t s);
 void prof_end(int kid, hipStream_t s);
@@ -127,6 +127,7 @@ int launch_map3(const MapGeom &g, int64_t n, int rho, int map, int strict, int32
                 unsigned long long *slots, hipStream_t s);
 int launch_map4(const MapGeom &g, int64_t n, int rho, int strict, int32_t *tiles,
                 unsigned long long *slots, hipStream_t s);
+int launch_decode(int m, const MapGeom &g, unsigned long long *slots, hipStream_t s);
 int launch_count(int m, const MapGeom &g, int64_t n, int rho, int map, int strict,
                  unsigned long long *slots, hipStream_t s);
 

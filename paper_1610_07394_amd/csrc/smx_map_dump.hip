@@ -248,6 +248,66 @@ int launch_count(int m, const MapGeom &g, int64_t n, int rho, int map, int stric
     return check_launch("simplex_count");
 }
 
+// Lane-parallel decode: every thread evaluates the map for kDecodeIds logical
+// block ids (id = 256 (kDecodeIds b + r) + t), so a launch measures the map's
+// arithmetic per id, free of block dispatch.  A mapped tile adds 1 to the count
+// and SplitMix64 of its colex rank (Y(Y+1)/2 + X, then the tetrahedral and
+// pentatope terms) to the checksum: over a bijection onto T_m these sums are
+// |T_m| and the checksum of the range [0, |T_m|).
+constexpr int kDecodeIds = 16;
+
+__device__ __forceinline__ uint64_t colex_rank(int m, const int T[4]) {
+    const uint64_t a = uint64_t(T[0]), b = uint64_t(T[1]), c = uint64_t(T[2]), d = uint64_t(T[3]);
+    uint64_t r = a + b * (b + 1) / 2;
+    if (m >= 3) r += c * (c + 1) * (c + 2) / 6;
+    if (m >= 4) r += d * (d + 1) * (d + 2) * (d + 3) / 24;
+    return r;
+}
+
+template <int MAP, int M>
+__global__ __launch_bounds__(kMapThreads) void decode_kernel(MapGeom g, unsigned long long *slots) {
+    __shared__ unsigned long long red[2][kMapThreads / kWave];
+    const uint64_t b = uint64_t(blockIdx.y) * gridDim.x + blockIdx.x;
+    unsigned long long cnt = 0, cs = 0;
+#pragma unroll 4
+    for (int r = 0; r < kDecodeIds; ++r) {
+        const uint64_t id = (b * kDecodeIds + uint64_t(r)) * kMapThreads + threadIdx.x;
+        if (id >= g.G) break;
+        uint64_t lin;
+        int T[4] = {0, 0, 0, 0};
+        bool ok;
+        if (M == 2) ok = tile2_of_id<MAP>(g, uint32_t(id), lin, T[0], T[1]);
+        else if (M == 3) ok = tile3_of_id<MAP>(g, uint32_t(id), lin, T[0], T[1], T[2]);
+        else ok = tile4_of_id<MAP>(g, uint32_t(id), lin, T);
+        if (ok) {
+            ++cnt;
+            cs += mix64(colex_rank(M, T));
+        }
+    }
+    const unsigned long long c = block_sum<unsigned long long, kMapThreads>(cnt, red[0]);
+    const unsigned long long h = block_sum<unsigned long long, kMapThreads>(cs, red[1]);
+    if (threadIdx.x == 0 && c != 0) {
+        unsigned long long *sl = slots + (b % kSlots) * kSlotStride;
+        atomicAdd(sl + 0, c);
+        atomicAdd(sl + 1, h);
+        atomicAdd(sl + 2, 1ull);
+    }
+}
+
+int launch_decode(int m, const MapGeom &g, unsigned long long *slots, hipStream_t s) {
+    prof_begin(K_DECODE, s);
+    for_each_launch(g, [&](auto Mk, const MapGeom &gg) {
+        constexpr int MAPK = decltype(Mk)::value;
+        const uint64_t per_block = uint64_t(kMapThreads) * kDecodeIds;
+        const dim3 grid = grid_for((gg.G + per_block - 1) / per_block, kMapThreads);
+        if (m == 2) hipLaunchKernelGGL((decode_kernel<MAPK, 2>), grid, dim3(kMapThreads), 0, s, gg, slots);
+        else if (m == 3) hipLaunchKernelGGL((decode_kernel<MAPK, 3>), grid, dim3(kMapThreads), 0, s, gg, slots);
+        else hipLaunchKernelGGL((decode_kernel<MAPK, 4>), grid, dim3(kMapThreads), 0, s, gg, slots);
+    });
+    prof_end(K_DECODE, s);
+    return check_launch("simplex decode");
+}
+
 template <int MAP>
 static void go_map2(const MapGeom &g, int64_t n, int rho, int lgrho, int strict, int32_t *tiles,
                     unsigned long long *slots, hipStream_t s) {

@@ -177,6 +177,17 @@ def test_validation_errors_before_any_device_work():
     assert L.smx_simplex_life(a, b, 100, 0, ctypes.c_void_p(8), null, 0, null) == 1
     assert b"workspace" in L.smx_last_error()
     assert L.smx_simplex_life(null, null, 0, 0, null, null, 0, null) == 0
+    # lane-parallel decode: bad m / nb / map, NULL stats, no workspace, from
+    # below on the 4-simplex
+    v = ctypes.c_void_p(256)
+    assert L.smx_simplex_decode(5, 8, 0, v, v, 1 << 20, null) == 1
+    assert L.smx_simplex_decode(2, -1, 0, v, v, 1 << 20, null) == 1
+    assert L.smx_simplex_decode(2, 8, 6, v, v, 1 << 20, null) == 1
+    assert L.smx_simplex_decode(2, 8, 0, null, v, 1 << 20, null) == 1
+    assert L.smx_simplex_decode(3, 8, 0, v, v, 8, null) == 1
+    assert b"workspace" in L.smx_last_error()
+    assert L.smx_simplex_decode(4, 8, 3, v, v, 1 << 20, null) == 3
+    assert L.smx_simplex_decode(2, 1 << 20, 1, v, v, 1 << 20, null) == 3  # bounding-box grid past 65535
     # probe: NULL output, block count, iterations
     assert L.smx_probe_valu(null, 1, 1, null) == 1
     assert L.smx_probe_valu(ctypes.c_void_p(256), 0, 1, null) == 1

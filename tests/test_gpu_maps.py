@@ -146,3 +146,19 @@ def test_count_kernel_closed_form(m, n, rho, kind, strict):
     assert int(s[0]) == oracle.simplex_volume(m, n, strict)
     assert int(s[2]) == (nb * (nb + 1) // 2 if m == 2 else nb * (nb + 1) * (nb + 2) // 6)
     assert int(s[3]) == smx.parallel_blocks(m, n, rho, kind)
+
+
+@pytest.mark.parametrize("m,nb", [(2, 1), (2, 2), (2, 13), (2, 64), (2, 1000), (2, 4096), (3, 1), (3, 5), (3, 17),
+                                  (3, 128), (3, 300), (4, 1), (4, 3), (4, 8), (4, 17), (4, 64)])
+@pytest.mark.parametrize("kind", KINDS)
+def test_decode_lane_parallel(m, nb, kind):
+    """The map decoded one lane per logical id: the mapped ids are exactly the
+    tiles of T_m (count and colex-rank checksum of a bijection), and every id of
+    the parallel space is decoded once."""
+    if m == 4 and kind == "lambda_below":
+        pytest.skip("from below is not defined for the 4-simplex")
+    vol = math.comb(nb + m - 1, m)
+    s = smx.simplex_decode(m, nb, kind).cpu().numpy()
+    assert int(s[0]) == vol
+    assert _u64(s[1]) == oracle.checksum_range(vol)
+    assert int(s[3]) == smx.parallel_blocks(m, nb, 1, kind)
