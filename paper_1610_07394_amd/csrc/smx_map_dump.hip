@@ -2,7 +2,9 @@
 // uniform, scalar unit), records its tile, and visits the elements of the tile
 // under the simplex mask, counting them and summing SplitMix64 of their ids.
 // This is the map with an almost empty body: it isolates the cost of the map
-// and of the blocks a map wastes (paper Sec. I and III).
+// and of the blocks a map wastes (paper Sec. I and III).  The count kernels
+// keep one block per tile with a closed-form count; the decode kernel drops
+// the block per tile and evaluates the map once per lane.
 #include "smx_device.h"
 #include "smx_internal.h"
 
