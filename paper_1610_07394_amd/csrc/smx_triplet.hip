@@ -29,7 +29,11 @@
 // with W_ab = sum over triplets holding the pair {a, b} of dE_t/ds_ab.  So each
 // triplet only adds three scalars.
 //
-// Block: 256 threads own the 32^3 triplets of tile (X, Y, Z), X <= Y <= Z.
+// Block: 256 threads own the 32^3 triplets of tile (X, Y, Z), X <= Y <= Z, one
+// tile after another: the grid is persistent (kAtPersistBlocks blocks, block b
+// taking logical ids b, b + grid, ...), and each tile's positions are loaded
+// while the previous tile's triplets run, so a block no longer starts with a
+// global load (the kernel took 64-65 ms with one block per tile, 55 ms so).
 //   1. positions of the three 32-particle tiles -> LDS;
 //   2. the 3 x 32 x 32 pair terms s, -4 s, d^5 -> LDS; d^5 = 0 for a pair that
 //      is out of order (i >= j, j >= k, i >= k) or past n, which zeroes R for
@@ -56,6 +60,9 @@
 namespace smx {
 
 constexpr int kTripThreads = 256;
+// persistent grid of the triplet kernels: 32 blocks per resident block slot
+// (256 CUs x 3 blocks); measured flat from 16 to 128
+constexpr int kAtPersistBlocks = 256 * 3 * 32;
 constexpr int kTripLd = kTripTile + 4;  // LDS row stride (floats)
 
 // DPP lane moves (all 64 lanes active): quad_perm xor 1 / xor 2 and
@@ -82,10 +89,6 @@ __global__ __launch_bounds__(kTripThreads, 3) void at_kernel(MapGeom g, const fl
                                                           int64_t ldx, float nu, double *__restrict__ G64,
                                                           double *__restrict__ eslots,
                                                           unsigned long long *sslots) {
-    uint64_t lin;
-    int TX, TY, TZ;
-    if (!tile3_of<MAP, true>(g, lin, TX, TY, TZ)) return;
-
     constexpr int PS = kTripTile * kTripLd;
     // LDS planes of PS floats.  Pair sets: ij (rows i, cols j), ki (rows k,
     // cols i), kj (rows k, cols j).
@@ -106,252 +109,284 @@ __global__ __launch_bounds__(kTripThreads, 3) void at_kernel(MapGeom g, const fl
     auto plane = [&](int i) -> float * { return L + i * PS; };
 
     const int t = threadIdx.x;
-    const int64_t base[3] = {int64_t(TX) * kTripTile, int64_t(TY) * kTripTile, int64_t(TZ) * kTripTile};
-
-    if (t < 3 * kTripTile) {
-        const int tile = t >> 5, a = t & 31;
-        const int64_t p = base[tile] + a;
+    // persistent blocks: block b takes logical ids b, b + nblk, ...; the next
+    // tile's positions are loaded while the current tile's triplets run
+    const uint64_t nblk = uint64_t(gridDim.x) * gridDim.y;
+    uint64_t id = uint64_t(blockIdx.y) * gridDim.x + blockIdx.x;
+    auto next_valid = [&](uint64_t &i, uint64_t &l, int &x, int &y, int &z) -> bool {
+        for (; i < g.G; i += nblk)
+            if (tile3_of_id<MAP>(g, uint32_t(i), l, x, y, z)) return true;
+        return false;
+    };
+    auto load_pos = [&](int x, int y, int z) {
         float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-        if (p < n) {
-            v.x = Xp[p * ldx + 0];
-            v.y = Xp[p * ldx + 1];
-            v.z = Xp[p * ldx + 2];
-        }
-        Pos[tile][a] = v;
-    }
-    __syncthreads();
-
-    // pair terms: set 0 rows i (X) cols j (Y); set 1 rows k (Z) cols i (X);
-    // set 2 rows k (Z) cols j (Y).  Valid iff the pair is in triplet order
-    // (i < j, i < k, j < k) and the larger index is < n.  Thread t takes
-    // column t % 32 and rows t / 32 + 8 it of every set; indices fit 32 bits
-    // (n < 2^31, tile bases < n + 32).  An interior tile (X < Y < Z, all of it
-    // below n: nearly every block) has only valid pairs and skips the test.
-    const bool interior = TX < TY && TY < TZ && base[2] + kTripTile <= n;
-    auto pair_terms = [&](auto full) {
-        constexpr bool FULL = decltype(full)::value;
-        const int c = t & 31, r0 = t >> 5;
-        const uint32_t un = uint32_t(n);
-        const uint32_t bt[3] = {uint32_t(base[0]), uint32_t(base[1]), uint32_t(base[2])};
-#pragma unroll
-        for (int set = 0; set < 3; ++set) {
-            const int ta = set == 0 ? 0 : 2, tb = set == 2 ? 1 : (set == 0 ? 1 : 0);
-            const float4 pb = Pos[tb][c];
-            const uint32_t gb = bt[tb] + uint32_t(c);
-#pragma unroll
-            for (int it = 0; it < 4; ++it) {
-                const int r = r0 + 8 * it;
-                const float4 pa = Pos[ta][r];
-                const float dx = pb.x - pa.x, dy = pb.y - pa.y, dz = pb.z - pa.z;
-                const float sv = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dx * dx));
-                const uint32_t ga = bt[ta] + uint32_t(r);
-                const bool valid = FULL || (set == 0 ? (ga < gb && gb < un) : (gb < ga && ga < un));
-                const float d = valid ? __builtin_amdgcn_rsqf(sv) : 0.f;
-                const float rs = d * d;
-                const int o = r * kTripLd + c;
-                plane(set == 0 ? S_IJ : S_KI + set - 1)[o] = sv;
-                plane(set == 0 ? D5_IJ : D5_KI + set - 1)[o] = (rs * rs) * d;
-                if (GRAD && set != 0) plane(M4_KI + set - 1)[o] = -4.f * sv;
+        if (t < 3 * kTripTile) {
+            const int tile = t >> 5, a = t & 31;
+            const int64_t p = int64_t(tile == 0 ? x : (tile == 1 ? y : z)) * kTripTile + a;
+            if (p < n) {
+                v.x = Xp[p * ldx + 0];
+                v.y = Xp[p * ldx + 1];
+                v.z = Xp[p * ldx + 2];
             }
         }
+        return v;
     };
-    if (interior) pair_terms(std::true_type{});
-    else pair_terms(std::false_type{});
-    __syncthreads();
+    uint64_t lin;
+    int TX, TY, TZ;
+    if (!next_valid(id, lin, TX, TY, TZ)) return;
+    float4 pv = load_pos(TX, TY, TZ);
+    while (true) {
+        const int64_t base[3] = {int64_t(TX) * kTripTile, int64_t(TY) * kTripTile, int64_t(TZ) * kTripTile};
+        if (t < 3 * kTripTile) Pos[t >> 5][t & 31] = pv;
+        __syncthreads();
+        uint64_t nid = id + nblk, nlin = 0;
+        int NX = 0, NY = 0, NZ = 0;
+        const bool more = next_valid(nid, nlin, NX, NY, NZ);
+        const float4 pnext = more ? load_pos(NX, NY, NZ) : make_float4(0.f, 0.f, 0.f, 0.f);
 
-    // lane = 16 row + 4 q + e;  ib = 4 (row >> 1) + q,  jb = 4 (row & 1) + e;
-    // the thread owns i in 4 ib + [0,4), j in 4 jb + [0,4), k in 8 kb + [0,8)
-    const int lane = t & 63, row = lane >> 4, q = (lane >> 2) & 3, el = lane & 3;
-    const int kb = __builtin_amdgcn_readfirstlane(t >> 6);  // wave index
-    const int ib = 4 * (row >> 1) + q, jb = 4 * (row & 1) + el;
-    float s1[4][4], f1[4][4], w1[4][4];
-#pragma unroll
-    for (int a = 0; a < 4; ++a) {
-        const int o = (4 * ib + a) * kTripLd + 4 * jb;
-        const float4 sv = *reinterpret_cast<const float4 *>(plane(S_IJ) + o);
-        const float4 fv = *reinterpret_cast<const float4 *>(plane(D5_IJ) + o);
-        s1[a][0] = sv.x; s1[a][1] = sv.y; s1[a][2] = sv.z; s1[a][3] = sv.w;
-        f1[a][0] = fv.x; f1[a][1] = fv.y; f1[a][2] = fv.z; f1[a][3] = fv.w;
-#pragma unroll
-        for (int b = 0; b < 4; ++b) w1[a][b] = 0.f;
-    }
-    // the (i, j) planes become the per-k weight planes
-    if (GRAD) __syncthreads();
-    float e = 0.f;
-    unsigned long long cnt = 0, cs = 0;
-
-#pragma unroll 1
-    for (int r = 0; r < 8; ++r) {
-        const int k = 8 * kb + r;
-        const int oi = k * kTripLd + 4 * ib, oj = k * kTripLd + 4 * jb;
-        const float4 s3v = *reinterpret_cast<const float4 *>(plane(S_KI) + oi);
-        const float4 f3v = *reinterpret_cast<const float4 *>(plane(D5_KI) + oi);
-        const float4 s2v = *reinterpret_cast<const float4 *>(plane(S_KJ) + oj);
-        const float4 f2v = *reinterpret_cast<const float4 *>(plane(D5_KJ) + oj);
-        const float s3a[4] = {s3v.x, s3v.y, s3v.z, s3v.w}, f3a[4] = {f3v.x, f3v.y, f3v.z, f3v.w};
-        const float s2a[4] = {s2v.x, s2v.y, s2v.z, s2v.w}, f2a[4] = {f2v.x, f2v.y, f2v.z, f2v.w};
-        float m3a[4], m2a[4];  // -4 s
-        if (GRAD) {
-            const float4 m3v = *reinterpret_cast<const float4 *>(plane(M4_KI) + oi);
-            const float4 m2v = *reinterpret_cast<const float4 *>(plane(M4_KJ) + oj);
-            m3a[0] = m3v.x; m3a[1] = m3v.y; m3a[2] = m3v.z; m3a[3] = m3v.w;
-            m2a[0] = m2v.x; m2a[1] = m2v.y; m2a[2] = m2v.z; m2a[3] = m2v.w;
-        } else {
-#pragma unroll
-            for (int b = 0; b < 4; ++b) m2a[b] = -4.f * s2a[b];
-        }
-        float w2[4] = {0.f, 0.f, 0.f, 0.f}, w3[4] = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-        for (int a = 0; a < 4; ++a)
-#pragma unroll
-            for (int b = 0; b < 4; ++b) {
-                const float sa = s1[a][b], sb = s2a[b], sc = s3a[a];
-                const float v = sb + sc;
-                const float t2n = v - sa;                   // -t2
-                const float u = sa + v;
-                const float q4 = -(m2a[b] * sc);            // 4 s2 s3
-                const float gg = __builtin_fmaf(-t2n, t2n, q4);  // g
-                const float y = u * gg;
-                const float P4 = sa * q4;                   // 4 P
-                const float R = f1[a][b] * (f2a[b] * f3a[a]);
-                if (!GRAD) {
-                    // 4 (P - 3/8 T) = 3/2 u g - 8 P
-                    e = __builtin_fmaf(__builtin_fmaf(1.5f, y, -2.f * P4), R, e);
-                } else {
-                    const float nQ = __builtin_fmaf(2.f, P4, -2.5f * y);  // -Q
-                    const float tu = u + u;
-                    const float K = __builtin_fmaf(tu, u, gg);
-                    // s_p (K - 4 u s_p) - Q;  K - 4 u s_1 = g - 2 u t2
-                    const float x1 = __builtin_fmaf(sa, __builtin_fmaf(tu, t2n, gg), nQ);
-                    const float x2 = __builtin_fmaf(sb, __builtin_fmaf(u, m2a[b], K), nQ);
-                    const float x3 = __builtin_fmaf(sc, __builtin_fmaf(u, m3a[a], K), nQ);
-                    w1[a][b] = __builtin_fmaf(R, x1, w1[a][b]);
-                    w2[b] = __builtin_fmaf(R, x2, w2[b]);
-                    w3[a] = __builtin_fmaf(R, x3, w3[a]);
+        // pair terms: set 0 rows i (X) cols j (Y); set 1 rows k (Z) cols i (X);
+        // set 2 rows k (Z) cols j (Y).  Valid iff the pair is in triplet order
+        // (i < j, i < k, j < k) and the larger index is < n.  Thread t takes
+        // column t % 32 and rows t / 32 + 8 it of every set; indices fit 32 bits
+        // (n < 2^31, tile bases < n + 32).  An interior tile (X < Y < Z, all of it
+        // below n: nearly every block) has only valid pairs and skips the test.
+        const bool interior = TX < TY && TY < TZ && base[2] + kTripTile <= n;
+        auto pair_terms = [&](auto full) {
+            constexpr bool FULL = decltype(full)::value;
+            const int c = t & 31, r0 = t >> 5;
+            const uint32_t un = uint32_t(n);
+            const uint32_t bt[3] = {uint32_t(base[0]), uint32_t(base[1]), uint32_t(base[2])};
+    #pragma unroll
+            for (int set = 0; set < 3; ++set) {
+                const int ta = set == 0 ? 0 : 2, tb = set == 2 ? 1 : (set == 0 ? 1 : 0);
+                const float4 pb = Pos[tb][c];
+                const uint32_t gb = bt[tb] + uint32_t(c);
+    #pragma unroll
+                for (int it = 0; it < 4; ++it) {
+                    const int r = r0 + 8 * it;
+                    const float4 pa = Pos[ta][r];
+                    const float dx = pb.x - pa.x, dy = pb.y - pa.y, dz = pb.z - pa.z;
+                    const float sv = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dx * dx));
+                    const uint32_t ga = bt[ta] + uint32_t(r);
+                    const bool valid = FULL || (set == 0 ? (ga < gb && gb < un) : (gb < ga && ga < un));
+                    const float d = valid ? __builtin_amdgcn_rsqf(sv) : 0.f;
+                    const float rs = d * d;
+                    const int o = r * kTripLd + c;
+                    plane(set == 0 ? S_IJ : S_KI + set - 1)[o] = sv;
+                    plane(set == 0 ? D5_IJ : D5_KI + set - 1)[o] = (rs * rs) * d;
+                    if (GRAD && set != 0) plane(M4_KI + set - 1)[o] = -4.f * sv;
                 }
-                if (STATS) {
-                    const int64_t gi = base[0] + 4 * ib + a, gj = base[1] + 4 * jb + b, gk = base[2] + k;
-                    if (gi < gj && gj < gk && gk < n) {
-                        ++cnt;
-                        cs += mix64(id_trip_lt(uint64_t(gi), uint64_t(gj), uint64_t(gk)));
+            }
+        };
+        if (interior) pair_terms(std::true_type{});
+        else pair_terms(std::false_type{});
+        __syncthreads();
+
+        // lane = 16 row + 4 q + e;  ib = 4 (row >> 1) + q,  jb = 4 (row & 1) + e;
+        // the thread owns i in 4 ib + [0,4), j in 4 jb + [0,4), k in 8 kb + [0,8)
+        const int lane = t & 63, row = lane >> 4, q = (lane >> 2) & 3, el = lane & 3;
+        const int kb = __builtin_amdgcn_readfirstlane(t >> 6);  // wave index
+        const int ib = 4 * (row >> 1) + q, jb = 4 * (row & 1) + el;
+        float s1[4][4], f1[4][4], w1[4][4];
+    #pragma unroll
+        for (int a = 0; a < 4; ++a) {
+            const int o = (4 * ib + a) * kTripLd + 4 * jb;
+            const float4 sv = *reinterpret_cast<const float4 *>(plane(S_IJ) + o);
+            const float4 fv = *reinterpret_cast<const float4 *>(plane(D5_IJ) + o);
+            s1[a][0] = sv.x; s1[a][1] = sv.y; s1[a][2] = sv.z; s1[a][3] = sv.w;
+            f1[a][0] = fv.x; f1[a][1] = fv.y; f1[a][2] = fv.z; f1[a][3] = fv.w;
+    #pragma unroll
+            for (int b = 0; b < 4; ++b) w1[a][b] = 0.f;
+        }
+        // the (i, j) planes become the per-k weight planes
+        if (GRAD) __syncthreads();
+        float e = 0.f;
+        unsigned long long cnt = 0, cs = 0;
+
+    #pragma unroll 1
+        for (int r = 0; r < 8; ++r) {
+            const int k = 8 * kb + r;
+            const int oi = k * kTripLd + 4 * ib, oj = k * kTripLd + 4 * jb;
+            const float4 s3v = *reinterpret_cast<const float4 *>(plane(S_KI) + oi);
+            const float4 f3v = *reinterpret_cast<const float4 *>(plane(D5_KI) + oi);
+            const float4 s2v = *reinterpret_cast<const float4 *>(plane(S_KJ) + oj);
+            const float4 f2v = *reinterpret_cast<const float4 *>(plane(D5_KJ) + oj);
+            const float s3a[4] = {s3v.x, s3v.y, s3v.z, s3v.w}, f3a[4] = {f3v.x, f3v.y, f3v.z, f3v.w};
+            const float s2a[4] = {s2v.x, s2v.y, s2v.z, s2v.w}, f2a[4] = {f2v.x, f2v.y, f2v.z, f2v.w};
+            float m3a[4], m2a[4];  // -4 s
+            if (GRAD) {
+                const float4 m3v = *reinterpret_cast<const float4 *>(plane(M4_KI) + oi);
+                const float4 m2v = *reinterpret_cast<const float4 *>(plane(M4_KJ) + oj);
+                m3a[0] = m3v.x; m3a[1] = m3v.y; m3a[2] = m3v.z; m3a[3] = m3v.w;
+                m2a[0] = m2v.x; m2a[1] = m2v.y; m2a[2] = m2v.z; m2a[3] = m2v.w;
+            } else {
+    #pragma unroll
+                for (int b = 0; b < 4; ++b) m2a[b] = -4.f * s2a[b];
+            }
+            float w2[4] = {0.f, 0.f, 0.f, 0.f}, w3[4] = {0.f, 0.f, 0.f, 0.f};
+    #pragma unroll
+            for (int a = 0; a < 4; ++a)
+    #pragma unroll
+                for (int b = 0; b < 4; ++b) {
+                    const float sa = s1[a][b], sb = s2a[b], sc = s3a[a];
+                    const float v = sb + sc;
+                    const float t2n = v - sa;                   // -t2
+                    const float u = sa + v;
+                    const float q4 = -(m2a[b] * sc);            // 4 s2 s3
+                    const float gg = __builtin_fmaf(-t2n, t2n, q4);  // g
+                    const float y = u * gg;
+                    const float P4 = sa * q4;                   // 4 P
+                    const float R = f1[a][b] * (f2a[b] * f3a[a]);
+                    if (!GRAD) {
+                        // 4 (P - 3/8 T) = 3/2 u g - 8 P
+                        e = __builtin_fmaf(__builtin_fmaf(1.5f, y, -2.f * P4), R, e);
+                    } else {
+                        const float nQ = __builtin_fmaf(2.f, P4, -2.5f * y);  // -Q
+                        const float tu = u + u;
+                        const float K = __builtin_fmaf(tu, u, gg);
+                        // s_p (K - 4 u s_p) - Q;  K - 4 u s_1 = g - 2 u t2
+                        const float x1 = __builtin_fmaf(sa, __builtin_fmaf(tu, t2n, gg), nQ);
+                        const float x2 = __builtin_fmaf(sb, __builtin_fmaf(u, m2a[b], K), nQ);
+                        const float x3 = __builtin_fmaf(sc, __builtin_fmaf(u, m3a[a], K), nQ);
+                        w1[a][b] = __builtin_fmaf(R, x1, w1[a][b]);
+                        w2[b] = __builtin_fmaf(R, x2, w2[b]);
+                        w3[a] = __builtin_fmaf(R, x3, w3[a]);
+                    }
+                    if (STATS) {
+                        const int64_t gi = base[0] + 4 * ib + a, gj = base[1] + 4 * jb + b, gk = base[2] + k;
+                        if (gi < gj && gj < gk && gk < n) {
+                            ++cnt;
+                            cs += mix64(id_trip_lt(uint64_t(gi), uint64_t(gj), uint64_t(gk)));
+                        }
                     }
                 }
+            if (GRAD) {
+                // energy (Euler): the sums of R x_p over this thread's triplets
+                e += ((w2[0] + w2[1]) + (w2[2] + w2[3])) + ((w3[0] + w3[1]) + (w3[2] + w3[3]));
+                // W_ik: sum the lane's partials over the quad (jb low bits); lane el
+                // stores i = 4 ib + el into plane (row & 1).  W_jk: sum over the
+                // row's quads (ib low bits); lane q stores j = 4 jb + q into plane
+                // (row >> 1).  Each entry has exactly one writer: no atomics.  The
+                // sums carry a factor s_p, removed after the loop.
+    #pragma unroll
+                for (int a = 0; a < 4; ++a) w3[a] = quad_allsum(w3[a]);
+    #pragma unroll
+                for (int b = 0; b < 4; ++b) w2[b] = rowquads_allsum(w2[b]);
+                // selects on the index bits (an equality chain becomes a branch
+            // per case, which costs registers the persistent loop needs)
+            const float v3 = (el & 2) ? ((el & 1) ? w3[3] : w3[2]) : ((el & 1) ? w3[1] : w3[0]);
+                const float v2 = (q & 2) ? ((q & 1) ? w2[3] : w2[2]) : ((q & 1) ? w2[1] : w2[0]);
+                plane(W_IK + (row & 1))[oi + el] = v3;
+                plane(W_JK + (row >> 1))[oj + q] = v2;
             }
+        }
+
+        // energy of the block, FP64 from the per-thread FP32 partials: sums of
+        // 4 (P - 3/8 T) R (energy only) or of R (x_1 + x_2 + x_3) = -12 (P - 3/8 T) R
         if (GRAD) {
-            // energy (Euler): the sums of R x_p over this thread's triplets
-            e += ((w2[0] + w2[1]) + (w2[2] + w2[3])) + ((w3[0] + w3[1]) + (w3[2] + w3[3]));
-            // W_ik: sum the lane's partials over the quad (jb low bits); lane el
-            // stores i = 4 ib + el into plane (row & 1).  W_jk: sum over the
-            // row's quads (ib low bits); lane q stores j = 4 jb + q into plane
-            // (row >> 1).  Each entry has exactly one writer: no atomics.  The
-            // sums carry a factor s_p, removed after the loop.
-#pragma unroll
-            for (int a = 0; a < 4; ++a) w3[a] = quad_allsum(w3[a]);
-#pragma unroll
-            for (int b = 0; b < 4; ++b) w2[b] = rowquads_allsum(w2[b]);
-            const float v3 = el == 0 ? w3[0] : (el == 1 ? w3[1] : (el == 2 ? w3[2] : w3[3]));
-            const float v2 = q == 0 ? w2[0] : (q == 1 ? w2[1] : (q == 2 ? w2[2] : w2[3]));
-            plane(W_IK + (row & 1))[oi + el] = v3;
-            plane(W_JK + (row >> 1))[oj + q] = v2;
+    #pragma unroll
+            for (int a = 0; a < 4; ++a) e += (w1[a][0] + w1[a][1]) + (w1[a][2] + w1[a][3]);
         }
-    }
+        const double eb = block_sum<double, kTripThreads>(double(e), red);
+        if (t == 0)
+            atomicAdd(eslots + (lin % kSlots) * kSlotStride + 0,
+                      eb * (GRAD ? -double(nu) / 12.0 : 0.25 * double(nu)));
+        if (STATS) {
+            const unsigned long long c = block_sum<unsigned long long, kTripThreads>(cnt, sred[0]);
+            const unsigned long long h = block_sum<unsigned long long, kTripThreads>(cs, sred[1]);
+            if (t == 0) stats_add(sslots, lin, c, h);
+        }
 
-    // energy of the block, FP64 from the per-thread FP32 partials: sums of
-    // 4 (P - 3/8 T) R (energy only) or of R (x_1 + x_2 + x_3) = -12 (P - 3/8 T) R
-    if (GRAD) {
-#pragma unroll
-        for (int a = 0; a < 4; ++a) e += (w1[a][0] + w1[a][1]) + (w1[a][2] + w1[a][3]);
-    }
-    const double eb = block_sum<double, kTripThreads>(double(e), red);
-    if (t == 0)
-        atomicAdd(eslots + (lin % kSlots) * kSlotStride + 0,
-                  eb * (GRAD ? -double(nu) / 12.0 : 0.25 * double(nu)));
-    if (STATS) {
-        const unsigned long long c = block_sum<unsigned long long, kTripThreads>(cnt, sred[0]);
-        const unsigned long long h = block_sum<unsigned long long, kTripThreads>(cs, sred[1]);
-        if (t == 0) stats_add(sslots, lin, c, h);
-    }
-
-    if (GRAD) {
-        // every wave is past the triplet loop (block_sum synchronised): the
-        // -4 s and d^5 planes (2..5) are dead, so plane 2 + kb takes this
-        // wave's slice of W_ij (its sums carry s_ij: divide, 0 outside the
-        // simplex)
-#pragma unroll
-        for (int a = 0; a < 4; ++a) {
-#pragma unroll
-            for (int b = 0; b < 4; ++b)
-                w1[a][b] = (interior || f1[a][b] != 0.f) ? w1[a][b] * __builtin_amdgcn_rcpf(s1[a][b]) : 0.f;
-            *reinterpret_cast<float4 *>(plane(2 + kb) + (4 * ib + a) * kTripLd + 4 * jb) =
-                make_float4(w1[a][0], w1[a][1], w1[a][2], w1[a][3]);
-        }
-        __syncthreads();
-        // one plane per pair set: W_ij -> plane 2, W_ik -> 6, W_jk -> 8 (in
-        // place), the last two divided by s (a pair outside the simplex has
-        // zero sums; s = 0 only for such pairs)
-        for (int o = t; o < kTripTile * kTripTile; o += kTripThreads) {
-            const int x = (o >> 5) * kTripLd + (o & 31);
-            plane(2)[x] = (plane(2)[x] + plane(3)[x]) + (plane(4)[x] + plane(5)[x]);
-            const float ski = plane(S_KI)[x], skj = plane(S_KJ)[x];
-            plane(W_IK)[x] = ski > 0.f ? (plane(W_IK)[x] + plane(W_IK + 1)[x]) * __builtin_amdgcn_rcpf(ski) : 0.f;
-            plane(W_JK)[x] = skj > 0.f ? (plane(W_JK)[x] + plane(W_JK + 1)[x]) * __builtin_amdgcn_rcpf(skj) : 0.f;
-        }
-        __syncthreads();
-        // transposes: W_ji [j][i] -> 3, W_ik [i][k] -> 7, W_jk [j][k] -> 9
-        for (int o = t; o < kTripTile * kTripTile; o += kTripThreads) {
-            const int r = o >> 5, c = o & 31, x = r * kTripLd + c, xt = c * kTripLd + r;
-            plane(3)[xt] = plane(2)[x];
-            plane(W_IK + 1)[xt] = plane(W_IK)[x];
-            plane(W_JK + 1)[xt] = plane(W_JK)[x];
-        }
-        __syncthreads();
-        // wave T < 3 takes tile T; lane = 32 h + a: particle a, pair set h.
-        //   X (i): h0 W_ij [i][j] (plane 2) with j,  h1 W_ik [i][k] (7) with k
-        //   Y (j): h0 W_ji [j][i] (3) with i,        h1 W_jk [j][k] (9) with k
-        //   Z (k): h0 W_ki [k][i] (6) with i,        h1 W_kj [k][j] (8) with j
-        // dE/dx_a = 2 nu sum_b W_ab (x_a - x_b) = 2 nu (x_a sum_b W_ab - sum_b W_ab x_b)
-        if (kb < 3) {
-            const int tile = kb, a = lane & 31, h = lane >> 5;
-            const int pl = tile == 0 ? (h == 0 ? 2 : W_IK + 1)
-                                     : (tile == 1 ? (h == 0 ? 3 : W_JK + 1) : (h == 0 ? W_IK : W_JK));
-            const int other = tile == 0 ? 1 + h : (tile == 1 ? 2 * h : h);
-            const float *W = plane(pl) + a * kTripLd;
-            float ws = 0.f, wx = 0.f, wy = 0.f, wz = 0.f;
-#pragma unroll 2
-            for (int b = 0; b < kTripTile; b += 4) {
-                const float4 w4 = *reinterpret_cast<const float4 *>(W + b);
-                const float wv[4] = {w4.x, w4.y, w4.z, w4.w};
-#pragma unroll
-                for (int c = 0; c < 4; ++c) {
-                    const float4 ot = Pos[other][b + c];
-                    ws += wv[c];
-                    wx = __builtin_fmaf(wv[c], ot.x, wx);
-                    wy = __builtin_fmaf(wv[c], ot.y, wy);
-                    wz = __builtin_fmaf(wv[c], ot.z, wz);
+        if (GRAD) {
+            // every wave is past the triplet loop (block_sum synchronised): the
+            // -4 s and d^5 planes (2..5) are dead, so plane 2 + kb takes this
+            // wave's slice of W_ij (its sums carry s_ij: divide, 0 outside the
+            // simplex)
+    #pragma unroll
+            for (int a = 0; a < 4; ++a) {
+    #pragma unroll
+                for (int b = 0; b < 4; ++b)
+                    w1[a][b] = (interior || f1[a][b] != 0.f) ? w1[a][b] * __builtin_amdgcn_rcpf(s1[a][b]) : 0.f;
+                *reinterpret_cast<float4 *>(plane(2 + kb) + (4 * ib + a) * kTripLd + 4 * jb) =
+                    make_float4(w1[a][0], w1[a][1], w1[a][2], w1[a][3]);
+            }
+            __syncthreads();
+            // one plane per pair set: W_ij -> plane 2, W_ik -> 6, W_jk -> 8 (in
+            // place), the last two divided by s (a pair outside the simplex has
+            // zero sums; s = 0 only for such pairs)
+            for (int o = t; o < kTripTile * kTripTile; o += kTripThreads) {
+                const int x = (o >> 5) * kTripLd + (o & 31);
+                plane(2)[x] = (plane(2)[x] + plane(3)[x]) + (plane(4)[x] + plane(5)[x]);
+                const float ski = plane(S_KI)[x], skj = plane(S_KJ)[x];
+                plane(W_IK)[x] = ski > 0.f ? (plane(W_IK)[x] + plane(W_IK + 1)[x]) * __builtin_amdgcn_rcpf(ski) : 0.f;
+                plane(W_JK)[x] = skj > 0.f ? (plane(W_JK)[x] + plane(W_JK + 1)[x]) * __builtin_amdgcn_rcpf(skj) : 0.f;
+            }
+            __syncthreads();
+            // transposes: W_ji [j][i] -> 3, W_ik [i][k] -> 7, W_jk [j][k] -> 9
+            for (int o = t; o < kTripTile * kTripTile; o += kTripThreads) {
+                const int r = o >> 5, c = o & 31, x = r * kTripLd + c, xt = c * kTripLd + r;
+                plane(3)[xt] = plane(2)[x];
+                plane(W_IK + 1)[xt] = plane(W_IK)[x];
+                plane(W_JK + 1)[xt] = plane(W_JK)[x];
+            }
+            __syncthreads();
+            // wave T < 3 takes tile T; lane = 32 h + a: particle a, pair set h.
+            //   X (i): h0 W_ij [i][j] (plane 2) with j,  h1 W_ik [i][k] (7) with k
+            //   Y (j): h0 W_ji [j][i] (3) with i,        h1 W_jk [j][k] (9) with k
+            //   Z (k): h0 W_ki [k][i] (6) with i,        h1 W_kj [k][j] (8) with j
+            // dE/dx_a = 2 nu sum_b W_ab (x_a - x_b) = 2 nu (x_a sum_b W_ab - sum_b W_ab x_b)
+            if (kb < 3) {
+                const int tile = kb, a = lane & 31, h = lane >> 5;
+                const int pl = tile == 0 ? (h == 0 ? 2 : W_IK + 1)
+                                         : (tile == 1 ? (h == 0 ? 3 : W_JK + 1) : (h == 0 ? W_IK : W_JK));
+                const int other = tile == 0 ? 1 + h : (tile == 1 ? 2 * h : h);
+                const float *W = plane(pl) + a * kTripLd;
+                float ws = 0.f, wx = 0.f, wy = 0.f, wz = 0.f;
+    #pragma unroll 2
+                for (int b = 0; b < kTripTile; b += 4) {
+                    const float4 w4 = *reinterpret_cast<const float4 *>(W + b);
+                    const float wv[4] = {w4.x, w4.y, w4.z, w4.w};
+    #pragma unroll
+                    for (int c = 0; c < 4; ++c) {
+                        const float4 ot = Pos[other][b + c];
+                        ws += wv[c];
+                        wx = __builtin_fmaf(wv[c], ot.x, wx);
+                        wy = __builtin_fmaf(wv[c], ot.y, wy);
+                        wz = __builtin_fmaf(wv[c], ot.z, wz);
+                    }
+                }
+                const float4 me = Pos[tile][a];
+                float gx = __builtin_fmaf(me.x, ws, -wx), gy = __builtin_fmaf(me.y, ws, -wy),
+                      gz = __builtin_fmaf(me.z, ws, -wz);
+                gx += __shfl_xor(gx, 32, kWave);
+                gy += __shfl_xor(gy, 32, kWave);
+                gz += __shfl_xor(gz, 32, kWave);
+                const int64_t gp = base[tile] + a;
+                if (h == 0 && gp < n) {
+                    // W is 3/8 of the accumulated sums
+                    const double sc = 0.75 * double(nu);
+                    atomicAdd(G64 + 3 * gp + 0, sc * double(gx));
+                    atomicAdd(G64 + 3 * gp + 1, sc * double(gy));
+                    atomicAdd(G64 + 3 * gp + 2, sc * double(gz));
                 }
             }
-            const float4 me = Pos[tile][a];
-            float gx = __builtin_fmaf(me.x, ws, -wx), gy = __builtin_fmaf(me.y, ws, -wy),
-                  gz = __builtin_fmaf(me.z, ws, -wz);
-            gx += __shfl_xor(gx, 32, kWave);
-            gy += __shfl_xor(gy, 32, kWave);
-            gz += __shfl_xor(gz, 32, kWave);
-            const int64_t gp = base[tile] + a;
-            if (h == 0 && gp < n) {
-                // W is 3/8 of the accumulated sums
-                const double sc = 0.75 * double(nu);
-                atomicAdd(G64 + 3 * gp + 0, sc * double(gx));
-                atomicAdd(G64 + 3 * gp + 1, sc * double(gy));
-                atomicAdd(G64 + 3 * gp + 2, sc * double(gz));
-            }
         }
+        __syncthreads();  // the next tile reuses every LDS buffer
+        if (!more) break;
+        id = nid;
+        lin = nlin;
+        TX = NX;
+        TY = NY;
+        TZ = NZ;
+        pv = pnext;
     }
 }
 
 template <int MAP, bool GRAD>
 static void go_at(const MapGeom &g, const float *X, int64_t n, int64_t ldx, float nu, double *G64,
                   double *eslots, unsigned long long *sslots, hipStream_t s) {
-    const dim3 grid = MAP == MAP_BBOX ? dim3(g.nb, g.nb, g.nb) : grid_for(g.G, kTripThreads);
+    const uint64_t nblk = g.G < uint64_t(kAtPersistBlocks) ? g.G : uint64_t(kAtPersistBlocks);
+    const dim3 grid(uint32_t(nblk > 0 ? nblk : 1));
     if (sslots)
         hipLaunchKernelGGL((at_kernel<MAP, GRAD, true>), grid, dim3(kTripThreads), 0, s, g, X, n, ldx, nu,
                            G64, eslots, sslots);
