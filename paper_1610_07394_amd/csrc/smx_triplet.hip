@@ -156,12 +156,12 @@ __global__ __launch_bounds__(kTripThreads, 3) void at_kernel(MapGeom g, const fl
             const int c = t & 31, r0 = t >> 5;
             const uint32_t un = uint32_t(n);
             const uint32_t bt[3] = {uint32_t(base[0]), uint32_t(base[1]), uint32_t(base[2])};
-    #pragma unroll
+#pragma unroll
             for (int set = 0; set < 3; ++set) {
                 const int ta = set == 0 ? 0 : 2, tb = set == 2 ? 1 : (set == 0 ? 1 : 0);
                 const float4 pb = Pos[tb][c];
                 const uint32_t gb = bt[tb] + uint32_t(c);
-    #pragma unroll
+#pragma unroll
                 for (int it = 0; it < 4; ++it) {
                     const int r = r0 + 8 * it;
                     const float4 pa = Pos[ta][r];
@@ -188,14 +188,14 @@ __global__ __launch_bounds__(kTripThreads, 3) void at_kernel(MapGeom g, const fl
         const int kb = __builtin_amdgcn_readfirstlane(t >> 6);  // wave index
         const int ib = 4 * (row >> 1) + q, jb = 4 * (row & 1) + el;
         float s1[4][4], f1[4][4], w1[4][4];
-    #pragma unroll
+#pragma unroll
         for (int a = 0; a < 4; ++a) {
             const int o = (4 * ib + a) * kTripLd + 4 * jb;
             const float4 sv = *reinterpret_cast<const float4 *>(plane(S_IJ) + o);
             const float4 fv = *reinterpret_cast<const float4 *>(plane(D5_IJ) + o);
             s1[a][0] = sv.x; s1[a][1] = sv.y; s1[a][2] = sv.z; s1[a][3] = sv.w;
             f1[a][0] = fv.x; f1[a][1] = fv.y; f1[a][2] = fv.z; f1[a][3] = fv.w;
-    #pragma unroll
+#pragma unroll
             for (int b = 0; b < 4; ++b) w1[a][b] = 0.f;
         }
         // the (i, j) planes become the per-k weight planes
@@ -203,7 +203,7 @@ __global__ __launch_bounds__(kTripThreads, 3) void at_kernel(MapGeom g, const fl
         float e = 0.f;
         unsigned long long cnt = 0, cs = 0;
 
-    #pragma unroll 1
+#pragma unroll 1
         for (int r = 0; r < 8; ++r) {
             const int k = 8 * kb + r;
             const int oi = k * kTripLd + 4 * ib, oj = k * kTripLd + 4 * jb;
@@ -220,13 +220,13 @@ __global__ __launch_bounds__(kTripThreads, 3) void at_kernel(MapGeom g, const fl
                 m3a[0] = m3v.x; m3a[1] = m3v.y; m3a[2] = m3v.z; m3a[3] = m3v.w;
                 m2a[0] = m2v.x; m2a[1] = m2v.y; m2a[2] = m2v.z; m2a[3] = m2v.w;
             } else {
-    #pragma unroll
+#pragma unroll
                 for (int b = 0; b < 4; ++b) m2a[b] = -4.f * s2a[b];
             }
             float w2[4] = {0.f, 0.f, 0.f, 0.f}, w3[4] = {0.f, 0.f, 0.f, 0.f};
-    #pragma unroll
+#pragma unroll
             for (int a = 0; a < 4; ++a)
-    #pragma unroll
+#pragma unroll
                 for (int b = 0; b < 4; ++b) {
                     const float sa = s1[a][b], sb = s2a[b], sc = s3a[a];
                     const float v = sb + sc;
@@ -261,16 +261,14 @@ __global__ __launch_bounds__(kTripThreads, 3) void at_kernel(MapGeom g, const fl
                     }
                 }
             if (GRAD) {
-                // energy (Euler): the sums of R x_p over this thread's triplets
-                e += ((w2[0] + w2[1]) + (w2[2] + w2[3])) + ((w3[0] + w3[1]) + (w3[2] + w3[3]));
                 // W_ik: sum the lane's partials over the quad (jb low bits); lane el
                 // stores i = 4 ib + el into plane (row & 1).  W_jk: sum over the
                 // row's quads (ib low bits); lane q stores j = 4 jb + q into plane
                 // (row >> 1).  Each entry has exactly one writer: no atomics.  The
                 // sums carry a factor s_p, removed after the loop.
-    #pragma unroll
+#pragma unroll
                 for (int a = 0; a < 4; ++a) w3[a] = quad_allsum(w3[a]);
-    #pragma unroll
+#pragma unroll
                 for (int b = 0; b < 4; ++b) w2[b] = rowquads_allsum(w2[b]);
                 // selects on the index bits (an equality chain becomes a branch
             // per case, which costs registers the persistent loop needs)
@@ -283,14 +281,16 @@ __global__ __launch_bounds__(kTripThreads, 3) void at_kernel(MapGeom g, const fl
 
         // energy of the block, FP64 from the per-thread FP32 partials: sums of
         // 4 (P - 3/8 T) R (energy only) or of R (x_1 + x_2 + x_3) = -12 (P - 3/8 T) R
+        // (with the gradient: the R x_1 sums here, the R x_2 and R x_3 sums from
+        // the weight planes after the loop)
         if (GRAD) {
-    #pragma unroll
+#pragma unroll
             for (int a = 0; a < 4; ++a) e += (w1[a][0] + w1[a][1]) + (w1[a][2] + w1[a][3]);
         }
-        const double eb = block_sum<double, kTripThreads>(double(e), red);
-        if (t == 0)
-            atomicAdd(eslots + (lin % kSlots) * kSlotStride + 0,
-                      eb * (GRAD ? -double(nu) / 12.0 : 0.25 * double(nu)));
+        if (!GRAD) {
+            const double eb = block_sum<double, kTripThreads>(double(e), red);
+            if (t == 0) atomicAdd(eslots + (lin % kSlots) * kSlotStride + 0, eb * (0.25 * double(nu)));
+        }
         if (STATS) {
             const unsigned long long c = block_sum<unsigned long long, kTripThreads>(cnt, sred[0]);
             const unsigned long long h = block_sum<unsigned long long, kTripThreads>(cs, sred[1]);
@@ -298,13 +298,13 @@ __global__ __launch_bounds__(kTripThreads, 3) void at_kernel(MapGeom g, const fl
         }
 
         if (GRAD) {
-            // every wave is past the triplet loop (block_sum synchronised): the
-            // -4 s and d^5 planes (2..5) are dead, so plane 2 + kb takes this
-            // wave's slice of W_ij (its sums carry s_ij: divide, 0 outside the
-            // simplex)
-    #pragma unroll
+            // every wave is past the triplet loop: the -4 s and d^5 planes (2..5)
+            // are dead, so plane 2 + kb takes this wave's slice of W_ij (its sums
+            // carry s_ij: divide, 0 outside the simplex)
+            __syncthreads();
+#pragma unroll
             for (int a = 0; a < 4; ++a) {
-    #pragma unroll
+#pragma unroll
                 for (int b = 0; b < 4; ++b)
                     w1[a][b] = (interior || f1[a][b] != 0.f) ? w1[a][b] * __builtin_amdgcn_rcpf(s1[a][b]) : 0.f;
                 *reinterpret_cast<float4 *>(plane(2 + kb) + (4 * ib + a) * kTripLd + 4 * jb) =
@@ -318,10 +318,13 @@ __global__ __launch_bounds__(kTripThreads, 3) void at_kernel(MapGeom g, const fl
                 const int x = (o >> 5) * kTripLd + (o & 31);
                 plane(2)[x] = (plane(2)[x] + plane(3)[x]) + (plane(4)[x] + plane(5)[x]);
                 const float ski = plane(S_KI)[x], skj = plane(S_KJ)[x];
-                plane(W_IK)[x] = ski > 0.f ? (plane(W_IK)[x] + plane(W_IK + 1)[x]) * __builtin_amdgcn_rcpf(ski) : 0.f;
-                plane(W_JK)[x] = skj > 0.f ? (plane(W_JK)[x] + plane(W_JK + 1)[x]) * __builtin_amdgcn_rcpf(skj) : 0.f;
+                const float rik = plane(W_IK)[x] + plane(W_IK + 1)[x], rjk = plane(W_JK)[x] + plane(W_JK + 1)[x];
+                e += rik + rjk;  // the R x_3 and R x_2 sums of the energy
+                plane(W_IK)[x] = ski > 0.f ? rik * __builtin_amdgcn_rcpf(ski) : 0.f;
+                plane(W_JK)[x] = skj > 0.f ? rjk * __builtin_amdgcn_rcpf(skj) : 0.f;
             }
-            __syncthreads();
+            const double eb = block_sum<double, kTripThreads>(double(e), red);  // synchronises the block
+            if (t == 0) atomicAdd(eslots + (lin % kSlots) * kSlotStride + 0, eb * (-double(nu) / 12.0));
             // transposes: W_ji [j][i] -> 3, W_ik [i][k] -> 7, W_jk [j][k] -> 9
             for (int o = t; o < kTripTile * kTripTile; o += kTripThreads) {
                 const int r = o >> 5, c = o & 31, x = r * kTripLd + c, xt = c * kTripLd + r;
@@ -342,11 +345,11 @@ __global__ __launch_bounds__(kTripThreads, 3) void at_kernel(MapGeom g, const fl
                 const int other = tile == 0 ? 1 + h : (tile == 1 ? 2 * h : h);
                 const float *W = plane(pl) + a * kTripLd;
                 float ws = 0.f, wx = 0.f, wy = 0.f, wz = 0.f;
-    #pragma unroll 2
+#pragma unroll 2
                 for (int b = 0; b < kTripTile; b += 4) {
                     const float4 w4 = *reinterpret_cast<const float4 *>(W + b);
                     const float wv[4] = {w4.x, w4.y, w4.z, w4.w};
-    #pragma unroll
+#pragma unroll
                     for (int c = 0; c < 4; ++c) {
                         const float4 ot = Pos[other][b + c];
                         ws += wv[c];
