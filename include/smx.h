@@ -128,6 +128,11 @@ int64_t smx_volume(int m, int64_t n, int strict);
  * Host only; -1 on bad arguments or overflow. */
 int64_t smx_parallel_blocks(int m, int64_t n, int rho, int map);
 
+/* The same count under the name of the paper's quantity: the volume |Pi| of
+ * the parallel space (Sec. I and III-A), in blocks.  Identical arguments,
+ * result and errors as smx_parallel_blocks.  Host only. */
+int64_t smx_parallel_volume(int m, int64_t n, int rho, int map);
+
 /* The tiles of launched blocks first .. first+count-1, written to host memory
  * tiles[count][m] in block order (-1 for a filtered block); the range must lie
  * in [0, smx_parallel_blocks(m, n, rho, map)).  Evaluated on the host by the

@@ -240,6 +240,8 @@ int64_t smx_parallel_blocks(int m, int64_t n, int rho, int map) {
     return int64_t(g.G);
 }
 
+int64_t smx_parallel_volume(int m, int64_t n, int rho, int map) { return smx_parallel_blocks(m, n, rho, map); }
+
 size_t smx_workspace_bytes(int op, int64_t n, int64_t d, int prec, int map) {
     (void)map;
     if (n < 0 || n > kMaxN) return 0;

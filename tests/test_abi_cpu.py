@@ -29,6 +29,22 @@ def test_library_exports_every_declared_symbol():
     assert not missing, missing
 
 
+def test_parallel_volume_is_parallel_blocks():
+    """smx_parallel_volume (the paper's |Pi|, in blocks) is the same count as
+    smx_parallel_blocks, errors included."""
+    L = ctypes.CDLL(smx.LIB_PATH)
+    for f in (L.smx_parallel_volume, L.smx_parallel_blocks):
+        f.argtypes = [ctypes.c_int, ctypes.c_int64, ctypes.c_int, ctypes.c_int]
+        f.restype = ctypes.c_int64
+    for m, n, rho in ((2, 1024, 16), (2, 1000, 16), (3, 8192, 8), (3, 100, 4), (4, 1024, 8), (2, 0, 16)):
+        for mp in range(6):
+            if m == 4 and mp == 3:
+                continue
+            assert L.smx_parallel_volume(m, n, rho, mp) == L.smx_parallel_blocks(m, n, rho, mp)
+    assert L.smx_parallel_volume(2, 64, 16, 0) == (4 // 2) * (4 + 1)  # Pi2 = (nb/2) x (nb+1), nb = 4
+    assert L.smx_parallel_volume(5, 64, 16, 0) == -1
+
+
 def test_version_and_volume():
     assert "gfx950" in smx.version()
     for n in (0, 1, 2, 3, 10, 1024, 65536):
