@@ -285,6 +285,24 @@ int smx_triplet_energy_backward(const float *d_X, int64_t n, int64_t ldx, const 
                                 int map, const double *d_gradE, float *d_dX, void *d_ws,
                                 size_t ws_bytes, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * computation as smx_triplet_energy_grad, with its workspace (energy slots and
+ * the FP64 gradient accumulator) taken from a static device array of the
+ * library instead of d_ws.  The array holds SMX_NOALLOC_MAX_N particles'
+ * worth (1.6 MB); each GPU the library runs on keeps its own copy until the
+ * process ends.  The call allocates nothing: no hipMalloc, hipFree or
+ * allocating library routine; the array's device address is looked up once
+ * per device, on the first call with that device current.
+ *   d_X, n, ldx, pot, map, d_E (nullable), d_G  as smx_triplet_energy_grad.
+ * n > SMX_NOALLOC_MAX_N returns SMX_EINVAL (use smx_triplet_energy_grad).
+ * Every call on one GPU shares that GPU's array and clears what must start at
+ * zero itself; calls that overlap on one GPU (different streams or threads
+ * without ordering between them) race on it and give wrong results. */
+#define SMX_NOALLOC_MAX_N 65536
+int smx_triplet_energy_grad_noalloc(const float *d_X, int64_t n, int64_t ldx, const smx_pot *pot, int map,
+                                    double *d_E, float *d_G, void *stream);
+
 /* Packed per-triplet Axilrod-Teller energies (Sec. I: a 3-simplex problem
  * whose output, like the packed EDM of a 2-simplex, is one value per simplex
  * element; it needs no reduction, so it is bound by the stores).

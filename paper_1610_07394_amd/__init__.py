@@ -17,7 +17,7 @@ import torch
 __all__ = [
     "MAPS", "PRECS", "SmxError", "Pot", "lib", "volume", "parallel_blocks", "map_tiles_host", "map_blocks_host",
     "workspace_bytes", "simplex_map2", "simplex_map3", "simplex_map4", "simplex_count", "triplet_packed", "triplet_packed_tiled", "triplet_tiled_len", "edm_tiled", "edm_tiled_len", "life_len", "simplex_life", "simplex_decode", "quad_contacts", "edm_packed", "triplet_energy",
-    "triplet_energy_grad", "triplet_energy_backward", "TripletEnergy", "profile_enable",
+    "triplet_energy_grad", "triplet_energy_grad_noalloc", "NOALLOC_MAX_N", "triplet_energy_backward", "TripletEnergy", "profile_enable",
     "profile_reset", "profile_read", "KERNELS", "select_library", "check_flags",
 ]
 
@@ -93,6 +93,7 @@ def lib():
         L.smx_triplet_energy.argtypes = [_vp, _i64, _i64, ctypes.POINTER(_Pot), _i32, _vp, _vp, _sz, _vp, _vp]
         L.smx_triplet_energy_grad.argtypes = [_vp, _i64, _i64, ctypes.POINTER(_Pot), _i32, _vp, _vp, _vp,
                                               _sz, _vp]
+        L.smx_triplet_energy_grad_noalloc.argtypes = [_vp, _i64, _i64, ctypes.POINTER(_Pot), _i32, _vp, _vp, _vp]
         L.smx_triplet_energy_backward.argtypes = [_vp, _i64, _i64, ctypes.POINTER(_Pot), _i32, _vp, _vp,
                                                   _vp, _sz, _vp]
         L.smx_scale_grad.argtypes = [_vp, _i64, _vp, _vp, _vp]
@@ -388,6 +389,27 @@ def triplet_energy_grad(X: torch.Tensor, pot: Pot = Pot(), map="lambda", ws=None
     c = pot._c()
     _check(lib().smx_triplet_energy_grad(xp, n, ldx, ctypes.byref(c), _map(map), _ptr(E), _ptr(G), _ptr(ws),
                                          ws.numel(), _stream()))
+    return E, G
+
+
+# largest n of smx_triplet_energy_grad_noalloc (its static device scratch)
+NOALLOC_MAX_N = 65536
+
+
+def triplet_energy_grad_noalloc(X: torch.Tensor, pot: Pot = Pot(), map="lambda", E=None, G=None):
+    """As triplet_energy_grad, through the entry point that takes its workspace
+    from the library's static device array (n <= NOALLOC_MAX_N).  E (FP64 [3])
+    and G (FP32 [n, 3]) may be passed in, preallocated; otherwise they are
+    allocated here, on the Python side."""
+    xp, n, ldx = _xarg(X)
+    E = E if E is not None else torch.empty(3, dtype=torch.float64, device=X.device)
+    G = G if G is not None else torch.empty((n, 3), dtype=torch.float32, device=X.device)
+    if (E.dtype != torch.float64 or E.numel() < 3 or not E.is_contiguous() or G.dtype != torch.float32
+            or G.numel() < 3 * n or not G.is_contiguous()):
+        raise ValueError("E must be a contiguous FP64 [3] and G a contiguous FP32 [n, 3]")
+    c = pot._c()
+    _check(lib().smx_triplet_energy_grad_noalloc(xp, n, ldx, ctypes.byref(c), _map(map), _dev(E, "E"),
+                                                 _dev(G, "G"), _stream()))
     return E, G
 
 

@@ -454,11 +454,15 @@ static int check_pot(const smx_pot *pot) {
     return SMX_OK;
 }
 
+static void *scratch_for_current_device();
+
 // Shared body of the triplet calls.  mode 0: energy; 1: energy + gradient;
-// 2: backward (gradient scaled by *d_gradE).
+// 2: backward (gradient scaled by *d_gradE).  static_ws: take the workspace
+// from the library's static device array (after every argument check, so a
+// bad call still touches no device state) instead of d_ws.
 static int triplet_run(int mode, const float *d_X, int64_t n, int64_t ldx, const smx_pot *pot, int map,
                        double *d_E, float *d_G, const double *d_gradE, void *d_ws, size_t ws_bytes,
-                       int64_t *d_stats, void *stream) {
+                       int64_t *d_stats, void *stream, bool static_ws = false) {
     if (n < 0) return fail(SMX_EINVAL, "n must be >= 0");
     if (n > kMaxN) return fail(SMX_EOVERFLOW, "n exceeds 2^31 - 1");
     if (ldx < 3) return fail(SMX_EINVAL, "ldx must be >= 3 (got %lld)", (long long)ldx);
@@ -470,13 +474,17 @@ static int triplet_run(int mode, const float *d_X, int64_t n, int64_t ldx, const
     if (mode == 2 && d_gradE == nullptr) return fail(SMX_EINVAL, "gradE must not be NULL");
     if (n > 0 && d_X == nullptr) return fail(SMX_EINVAL, "X must not be NULL");
     const TripWs w = trip_ws(n);
-    if (d_ws == nullptr || ws_bytes < w.total)
+    if (!static_ws && (d_ws == nullptr || ws_bytes < w.total))
         return fail(SMX_EINVAL, "workspace of %zu bytes required (got %zu)", w.total, ws_bytes);
     MapGeom g3, g2;
     const int64_t nb3 = (n + kTripTile - 1) / kTripTile, nb2 = (n + kLjTile - 1) / kLjTile;
     const bool do_at = pot->at_on && n >= 3, do_lj = pot->lj_on && n >= 2;
     if (do_at && !make_geom(3, nb3, map, g3)) return g_status;
     if (do_lj && !make_geom(2, nb2, map, g2)) return g_status;
+    if (static_ws) {
+        if ((d_ws = scratch_for_current_device()) == nullptr) return g_status;
+        ws_bytes = w.total;
+    }
 
     char *ws = reinterpret_cast<char *>(d_ws);
     double *eslots = reinterpret_cast<double *>(ws + w.eslots);
@@ -515,6 +523,57 @@ int smx_triplet_energy_backward(const float *d_X, int64_t n, int64_t ldx, const 
                                 const double *d_gradE, float *d_dX, void *d_ws, size_t ws_bytes,
                                 void *stream) {
     return triplet_run(2, d_X, n, ldx, pot, map, nullptr, d_dX, d_gradE, d_ws, ws_bytes, nullptr, stream);
+}
+
+// ------------------------------------------------- allocation-free variant
+// Workspace of smx_triplet_energy_grad_noalloc: a file-scope device array.  In
+// host code its name is a host-side stand-in, not a device address; the
+// address is taken per device with hipGetSymbolAddress (each GPU holds its own
+// copy) and only that address is passed on.
+constexpr int64_t kNoallocMaxN = SMX_NOALLOC_MAX_N;
+constexpr size_t kNoallocBytes = 3 * kSlotBytes + size_t(kNoallocMaxN) * 3 * 8;
+static __device__ __align__(256) unsigned char scratch[kNoallocBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+// Device address of `scratch` on the current device, looked up on the first
+// call per device; nullptr (with the error recorded) on failure.
+static void *scratch_for_current_device() {
+    int dev = -1;
+    const hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) {
+        fail(SMX_EHIP, "hipGetDevice: %s", hipGetErrorString(e));
+        return nullptr;
+    }
+    if (dev < 0 || dev >= kMaxDevices) {
+        fail(SMX_EUNSUPPORTED, "device %d is past the %d devices the static scratch supports", dev, kMaxDevices);
+        return nullptr;
+    }
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch_ptr[dev] == nullptr) {
+        void *p = nullptr;
+        const hipError_t r = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (r != hipSuccess || p == nullptr) {
+            fail(SMX_EHIP, "hipGetSymbolAddress(scratch) on device %d: %s", dev, hipGetErrorString(r));
+            return nullptr;
+        }
+        g_scratch_ptr[dev] = p;
+    }
+    return g_scratch_ptr[dev];
+}
+
+int smx_triplet_energy_grad_noalloc(const float *d_X, int64_t n, int64_t ldx, const smx_pot *pot, int map,
+                                    double *d_E, float *d_G, void *stream) {
+    if (n > kNoallocMaxN)
+        return fail(SMX_EINVAL, "n = %lld exceeds the static scratch limit of %lld particles "
+                    "(smx_triplet_energy_grad takes a workspace of any size)",
+                    (long long)n, (long long)kNoallocMaxN);
+    static_assert(kNoallocBytes >= 3 * kSlotBytes + size_t(kNoallocMaxN) * 3 * 8, "scratch holds trip_ws(max n)");
+    return triplet_run(1, d_X, n, ldx, pot, map, d_E, d_G, nullptr, nullptr, 0, nullptr, stream, true);
 }
 
 int smx_probe_valu(float *d_out, int64_t blocks, int iters, void *stream) {

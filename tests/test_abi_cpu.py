@@ -230,6 +230,22 @@ def test_validation_errors_before_any_device_work():
                                 ctypes.c_void_p(256), 1 << 20, null, null) == 1
     assert L.smx_triplet_energy_backward(ctypes.c_void_p(256), 10, 3, ctypes.byref(pot), 0, null,
                                          ctypes.c_void_p(256), ctypes.c_void_p(256), 1 << 20, null) == 1
+    # the allocation-free variant checks its arguments, and its size limit, first
+    L.smx_triplet_energy_grad_noalloc.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64,
+                                                  ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p,
+                                                  ctypes.c_void_p, ctypes.c_void_p]
+    pp = ctypes.cast(ctypes.byref(pot), ctypes.c_void_p)
+    assert L.smx_triplet_energy_grad_noalloc(ctypes.c_void_p(256), 65537, 3, pp, 0, null,
+                                             ctypes.c_void_p(256), null) == 1
+    assert b"static scratch limit" in L.smx_last_error()
+    assert L.smx_triplet_energy_grad_noalloc(ctypes.c_void_p(256), -1, 3, pp, 0, null, ctypes.c_void_p(256),
+                                             null) == 1
+    assert L.smx_triplet_energy_grad_noalloc(ctypes.c_void_p(256), 10, 3, pp, 0, null, null, null) == 1
+    assert b"gradient" in L.smx_last_error()
+    assert L.smx_triplet_energy_grad_noalloc(ctypes.c_void_p(256), 10, 2, pp, 0, null, ctypes.c_void_p(256),
+                                             null) == 1
+    assert L.smx_triplet_energy_grad_noalloc(ctypes.c_void_p(256), 10, 3, null, 0, null, ctypes.c_void_p(256),
+                                             null) == 1
     assert L.smx_scale_grad(null, -1, null, null, null) == 1
     assert L.smx_scale_grad(null, 0, null, null, null) == 0
     ms, cnt = ctypes.c_double(), ctypes.c_int64()
