@@ -1,9 +1,14 @@
-"""Write tests/golden/expected.json: oracle values too slow to recompute in a
-test run (whole-simplex checksums at full sizes; the Axilrod-Teller + LJ
-energy and sampled gradient rows of the n = 8192 workload).
+"""Write oracle values too slow to recompute in a test run.
+
+tests/golden/expected.json: whole-simplex checksums at full sizes, the
+Axilrod-Teller + LJ energy and sampled gradient rows of the n = 8192 workload.
+tests/golden/grad_n8192.npz (--full-grad): the oracle's full FP64 gradient
+of that workload, Axilrod-Teller ("at", all C(8192, 3) triplets) and
+Lennard-Jones ("lj") separately, each [8192, 3].
 
 Calls only the oracle and the seeded input generators:
-    python tests/golden/make_golden.py
+    python tests/golden/make_golden.py             # expected.json
+    python tests/golden/make_golden.py --full-grad # grad_n8192.npz (minutes)
 """
 from __future__ import annotations
 
@@ -22,6 +27,7 @@ import oracle  # noqa: E402
 import synth  # noqa: E402
 
 OUT = os.path.join(os.path.dirname(os.path.abspath(__file__)), "expected.json")
+OUT_GRAD = os.path.join(os.path.dirname(os.path.abspath(__file__)), "grad_n8192.npz")
 
 # sampled particles of the n = 8192 gradient check: tile edges of 32 and 64,
 # both ends, plus seeded random picks
@@ -67,5 +73,18 @@ def main():
     print("wrote", OUT)
 
 
+def full_grad():
+    X = synth.workload_input("at_lj_n8192")
+    t0 = time.time()
+    at = oracle.at_grad(X, 1.0)
+    print("at grad", time.time() - t0, flush=True)
+    lj = oracle.lj_grad(X, 1.0, 1.0, 3.0)
+    np.savez(OUT_GRAD, at=at, lj=lj, input_sha256=np.array(sha(X)))
+    print("wrote", OUT_GRAD, "threads", oracle.threads())
+
+
 if __name__ == "__main__":
-    main()
+    if "--full-grad" in sys.argv[1:]:
+        full_grad()
+    else:
+        main()

@@ -22,6 +22,7 @@ import synth
 pytestmark = pytest.mark.gpu
 
 GOLD = os.path.join(os.path.dirname(__file__), "golden", "expected.json")
+GRAD_FULL = os.path.join(os.path.dirname(__file__), "golden", "grad_n8192.npz")
 KINDS = ["lambda", "bbox", "linear", "lambda_below", "recursive", "recursive_launch"]
 AT = smx.Pot(nu=1.0, at=True, lj=False)
 ATLJ = smx.Pot(nu=1.0, at=True, lj=True, eps=1.0, sigma=1.0, rc=3.0)
@@ -191,14 +192,17 @@ def test_at_n2048_full_gradient():
 
 
 def test_at_lj_n8192_full_size():
-    """The n = 8192 workload (9.2e10 triplets + 3.4e7 pairs): energies and
-    sampled gradient rows against oracle values, all maps, exact counts."""
+    """The n = 8192 workload (9.2e10 triplets + 3.4e7 pairs): energies and the
+    whole gradient, all 8192 rows, against the oracle's FP64 values (stored by
+    tests/golden/make_golden.py), on every map, with the error scaled by the
+    oracle's largest force; exact counts and checksums."""
     gold = json.load(open(GOLD))
     g = gold["at_lj_n8192"]
     X = synth.workload_input("at_lj_n8192")
+    full = np.load(GRAD_FULL)
+    assert str(full["input_sha256"]) == gold["inputs"]["at_lj_n8192"]["sha256"]
+    ref = full["at"] + full["lj"]
     Xt = _gpu(X)
-    rows = np.array(g["grad_rows"])
-    ref_rows = np.array(g["at_grad_rows"]) + np.array(g["lj_grad_rows"])
     for kind in KINDS:
         print(f"  n=8192 {kind}", flush=True)
         E, G = smx.triplet_energy_grad(Xt, ATLJ, kind)
@@ -206,10 +210,9 @@ def test_at_lj_n8192_full_size():
         E = E.cpu().numpy()
         assert abs(E[1] - g["at_energy"]) <= 1e-5 * abs(g["at_energy"])
         assert abs(E[2] - g["lj_energy"]) <= 1e-5 * abs(g["lj_energy"])
-        Gr = G.cpu().numpy().astype(np.float64)[rows]
-        err = float(np.linalg.norm(Gr - ref_rows, axis=1).max() / np.linalg.norm(G.cpu().numpy(), axis=1).max())
+        err = _fmetric(G.cpu().numpy().astype(np.float64), ref)
         print(f"  {kind}: E_at rel {abs(E[1] - g['at_energy']) / abs(g['at_energy']):.2e} "
-              f"rows err {err:.2e}", flush=True)
+              f"gradient err {err:.2e} (all rows)", flush=True)
         assert err <= 1e-5
     _, s = smx.triplet_energy(Xt, ATLJ, "lambda", stats=True)
     s = s.cpu().numpy()

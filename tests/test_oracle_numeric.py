@@ -193,6 +193,37 @@ def test_at_grad_rows_matches_full():
                                atol=1e-13 * np.abs(G).max())
 
 
+def test_stored_full_gradient_n8192():
+    """The stored FP64 gradient of the n = 8192 workload (written by
+    tests/golden/make_golden.py from the oracle's full triple loop): it belongs
+    to the workload's input, it satisfies the invariants of a translation- and
+    rotation-invariant energy homogeneous of degree -9 (AT) against the stored
+    energy, and its sampled rows equal those of the oracle's other loop (one
+    particle against all pairs), stored independently."""
+    import json
+    import os
+
+    here = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+    gold = json.load(open(os.path.join(here, "expected.json")))
+    full = np.load(os.path.join(here, "grad_n8192.npz"))
+    X = synth.workload_input("at_lj_n8192")
+    import hashlib
+    assert str(full["input_sha256"]) == hashlib.sha256(np.ascontiguousarray(X).tobytes()).hexdigest()
+    at, lj = full["at"], full["lj"]
+    assert at.shape == lj.shape == (8192, 3)
+    g = gold["at_lj_n8192"]
+    Xd = X.astype(np.float64)
+    scale = np.abs(at).max()
+    np.testing.assert_allclose(at.sum(axis=0), 0.0, atol=1e-11 * scale)
+    assert float((Xd * at).sum()) == pytest.approx(-9.0 * g["at_energy"], rel=1e-9)
+    np.testing.assert_allclose(np.cross(Xd, at).sum(axis=0), 0.0, atol=1e-9 * scale * np.abs(Xd).max())
+    rows = np.array(g["grad_rows"])
+    np.testing.assert_allclose(at[rows], np.array(g["at_grad_rows"]), rtol=1e-10, atol=1e-12 * scale)
+    lscale = np.abs(lj).max()
+    np.testing.assert_allclose(lj[rows], np.array(g["lj_grad_rows"]), rtol=1e-12, atol=1e-14 * lscale)
+    np.testing.assert_allclose(lj, oracle.lj_grad(X, 1.0, 1.0, 3.0), rtol=1e-12, atol=1e-14 * lscale)
+
+
 # ------------------------------------------------------------------ Lennard-Jones
 def test_lj_closed_forms():
     rmin = 2.0 ** (1 / 6)
