@@ -233,6 +233,51 @@ def main():
             "lj_ms": kavg["lj"], "triplets_per_s": tri / t,
             "alu_tflops": AT_FLOPS_FWD_BWD * tri / t / 1e12, "alu_frac": AT_FLOPS_FWD_BWD * tri / t / PEAK_FP32}
 
+    # the Axilrod-Teller workload at n = 2048 (forward + backward, one fused pass)
+    # and the energy-only kernel at n = 2048 and n = 8192, beside the step
+    if "at" in only:
+        log("Axilrod-Teller n = 2048 forward + backward, energy-only kernels")
+        X4 = torch.from_numpy(synth.workload_input("at_n2048")).to(dev)
+        at_only = smx.Pot(nu=1.0, at=True, lj=False)
+        ws4 = torch.empty(smx.workspace_bytes(2, X4.shape[0]), dtype=torch.uint8, device=dev)
+
+        def timed(fn, kernel, reps):
+            fn()
+            torch.cuda.synchronize()
+            smx.profile_enable(True)
+            smx.profile_reset()
+            for _ in range(reps):
+                fn()
+            ms, c = smx.profile_read(kernel)
+            smx.profile_enable(False)
+            return ms / c
+
+        n4 = X4.shape[0]
+        tri4 = math.comb(n4, 3)
+        reps = max(args.steps, 10)
+        t_fb = timed(lambda: smx.triplet_energy_grad(X4, at_only, "lambda", ws=ws4), "triplet_grad", reps)
+        t_fb_bb = timed(lambda: smx.triplet_energy_grad(X4, at_only, "bbox", ws=ws4), "triplet_grad", reps)
+        t_f = timed(lambda: smx.triplet_energy(X4, at_only, "lambda", ws=ws4), "triplet_energy", reps)
+        t_f8 = timed(lambda: smx.triplet_energy(X5, at_only, "lambda", ws=ws5), "triplet_energy", args.steps)
+        tri5 = math.comb(N_AT, 3)
+        comps["at_n2048_fwd_bwd"] = {
+            "triplets": tri4, "kernel_ms": t_fb, "bbox_kernel_ms": t_fb_bb, "speedup_lambda_vs_bbox": t_fb_bb / t_fb,
+            "triplets_per_s": tri4 / (t_fb / 1e3),
+            "alu_tflops": AT_FLOPS_FWD_BWD * tri4 / (t_fb / 1e3) / 1e12,
+            "alu_frac": AT_FLOPS_FWD_BWD * tri4 / (t_fb / 1e3) / PEAK_FP32,
+            "per_unit": "80 declared flops per triplet (20 forward + 60 backward), 1.4296e9 triplets per launch"}
+        comps["at_n2048_fwd"] = {
+            "triplets": tri4, "kernel_ms": t_f, "triplets_per_s": tri4 / (t_f / 1e3),
+            "alu_tflops": AT_FLOPS_FWD * tri4 / (t_f / 1e3) / 1e12,
+            "alu_frac": AT_FLOPS_FWD * tri4 / (t_f / 1e3) / PEAK_FP32,
+            "per_unit": "20 declared flops per triplet (forward), 1.4296e9 triplets per launch"}
+        comps["at_n8192_fwd"] = {
+            "triplets": tri5, "kernel_ms": t_f8, "triplets_per_s": tri5 / (t_f8 / 1e3),
+            "alu_tflops": AT_FLOPS_FWD * tri5 / (t_f8 / 1e3) / 1e12,
+            "alu_frac": AT_FLOPS_FWD * tri5 / (t_f8 / 1e3) / PEAK_FP32,
+            "per_unit": "20 declared flops per triplet (forward), 9.159e10 triplets per launch"}
+        del ws4
+
     # packed per-triplet energies, n = 2048 (the write-bound 3-simplex workload;
     # measured beside the step, not part of it)
     if "at" in only and not args.no_compare:
@@ -432,9 +477,18 @@ def main():
 
     # ---- CPU baseline: the FP64 oracle on a bounded sample, host cores
     cpu = None
+    accuracy = None
     if not args.no_cpu_baseline:
         log("CPU baseline (oracle)")
         cpu = cpu_baseline(only, elements, total_elems)
+        log("measured errors against the oracle")
+        accuracy = measured_errors(only, smx, torch, dev, X2, X3, X5, D2, D3, ws3, ws5, pot)
+        for name, key in (("edm_fp32_n65536_d64", "edm_fp32_n65536_d64"),
+                          ("edm_split_bf16_n32768_d512", "gram_split_bf16_n32768_d512"),
+                          ("edm_bf16_n32768_d512", "gram_bf16_n32768_d512"),
+                          ("at_lj_n8192_fwd_bwd", "at_lj_n8192"), ("at_n2048_fwd_bwd", "at_n2048")):
+            if name in comps and key in accuracy:
+                comps[name]["max_err"] = accuracy[key]
 
     out = {
         "metric": "simplex elements/sec (lambda map) for packed EDM + AT/LJ fwd+bwd",
@@ -460,6 +514,7 @@ def main():
         "kernel_ms_avg": kavg,
         "compare": compare,
         "cpu_baseline": cpu,
+        "accuracy": accuracy,
     }
     print(json.dumps(out))
 
@@ -493,6 +548,89 @@ def valu_ceiling(smx, torch, dev):
         ms = ev[0].elapsed_time(ev[1])
         best = ms if best is None else min(best, ms)
     return blocks * 256 * iters * 64 / (best / 1e3)
+
+
+def measured_errors(only, smx, torch, dev, X2, X3, X5, D2, D3, ws3, ws5, pot):
+    """Errors of the GPU results against the FP64 oracle on bounded samples
+    (the same metrics as the parity tests): packed EDM rows 0..R of each
+    workload, every precision of the Gram input; Axilrod-Teller + LJ energies
+    and gradient rows at n = 8192, the whole energy and gradient at n = 2048."""
+    import json
+
+    import numpy as np
+
+    import oracle
+    import synth
+
+    out = {}
+    refs = {}
+
+    def edm_err(Xn, Dg, rows, scale_form):
+        n = Xn.shape[0]
+        if (n, rows) not in refs:
+            refs[(n, rows)] = oracle.edm_rows(Xn, 0, rows)
+        ref = refs[(n, rows)]
+        got = Dg[:ref.shape[0]].cpu().numpy().astype(np.float64)
+        ii = np.repeat(np.arange(rows), n - np.arange(rows))
+        jj = np.concatenate([np.arange(i, n) for i in range(rows)])
+        diag = ii == jj
+        off = ~diag
+        res = {"pairs": int(ref.shape[0]), "rows": f"0..{rows}", "diagonal_exact_zero": bool((got[diag] == 0).all())}
+        rel = np.abs(got[off] - ref[off]) / ref[off]
+        res["max_rel_err"] = float(rel.max())
+        res["mean_rel_err"] = float(rel.mean())
+        if scale_form:
+            nrm = (Xn.astype(np.float64) ** 2).sum(1)
+            sc = np.abs(got[off] - ref[off]) / (nrm[ii[off]] + nrm[jj[off]])
+            res["max_err_vs_norms"] = float(sc.max())
+            res["metric"] = "|D^ - D| / (|x_i|^2 + |x_j|^2), off the diagonal (max_rel_err: |D^ - D| / D)"
+            res["value"] = res["max_err_vs_norms"]
+        else:
+            res["metric"] = "|D^ - D| / D, off the diagonal"
+            res["value"] = res["max_rel_err"]
+        return res
+
+    if "edm" in only:
+        smx.edm_packed(X2, "lambda", "fp32", out=D2)
+        torch.cuda.synchronize()
+        out["edm_fp32_n65536_d64"] = edm_err(synth.workload_input("edm_n65536_d64"), D2, 1024, False)
+    if "gram" in only:
+        Xg = synth.workload_input("gram_n32768_d512")
+        for prec, key in (("bf16", "gram_bf16_n32768_d512"), ("split_bf16", "gram_split_bf16_n32768_d512"),
+                          ("fp32", "gram_input_fp32_diff_n32768_d512")):
+            smx.edm_packed(X3, "lambda", prec, out=D3, ws=ws3)
+            torch.cuda.synchronize()
+            out[key] = edm_err(Xg, D3, 1024, True)
+    if "at" in only:
+        X = synth.workload_input("at_lj_n8192")
+        E, G = smx.triplet_energy_grad(X5, pot, "lambda", ws=ws5)
+        torch.cuda.synchronize()
+        E = E.cpu().numpy()
+        G = G.cpu().numpy().astype(np.float64)
+        rows = list(range(0, N_AT, 256))
+        g_ref = oracle.at_grad_rows(X, rows, 1.0) + oracle.lj_grad(X, 1.0, 1.0, 3.0)[rows]
+        lj_ref = oracle.lj_energy(X, 1.0, 1.0, 3.0)
+        res = {"metric": "max_i |G^_i - G_i| / max_i |G_i| over the sampled rows (forces = -G)",
+               "gradient_rows": len(rows),
+               "value": float(np.linalg.norm(G[rows] - g_ref, axis=1).max() / np.linalg.norm(g_ref, axis=1).max()),
+               "lj_energy_rel_err": abs(E[2] - lj_ref) / abs(lj_ref)}
+        gold = os.path.join(ROOT, "tests", "golden", "expected.json")
+        if os.path.exists(gold):  # the full AT energy, stored by the oracle-only golden script
+            e_at = json.load(open(gold))["at_lj_n8192"]["at_energy"]
+            res["at_energy_rel_err"] = abs(E[1] - e_at) / abs(e_at)
+        out["at_lj_n8192"] = res
+        X4n = synth.workload_input("at_n2048")
+        X4 = torch.from_numpy(X4n).to(dev)
+        at_only = smx.Pot(nu=1.0, at=True, lj=False)
+        E4, G4 = smx.triplet_energy_grad(X4, at_only, "lambda")
+        torch.cuda.synchronize()
+        e_ref = oracle.at_energy(X4n, 1.0)
+        g4_ref = oracle.at_grad(X4n, 1.0)
+        G4 = G4.cpu().numpy().astype(np.float64)
+        out["at_n2048"] = {"metric": "max_i |G^_i - G_i| / max_i |G_i| over all 2048 rows (forces = -G)",
+                           "value": float(np.linalg.norm(G4 - g4_ref, axis=1).max() / np.linalg.norm(g4_ref, axis=1).max()),
+                           "energy_rel_err": abs(float(E4[0].item()) - e_ref) / abs(e_ref)}
+    return out
 
 
 def cpu_baseline(only, elements, total_elems):

@@ -9,10 +9,10 @@
 // at 0 and the diagonal is set to exactly 0 (the Gram form cancels there).
 //
 // Block: 256 threads (4 waves as 2 x 2), tile 128 x 128 of the packed upper
-// triangle, each wave 64 x 64 in MFMA tiles of 32 x 32.  K advances in
-// chunks of 32 BF16 through two alternating LDS buffers filled directly from
-// global memory in MFMA fragment order (see the staging notes below), so the
-// loads of chunk s + 1 are in flight while the matrix cores run chunk s.
+// triangle, each wave 64 x 64 in MFMA tiles of 32 x 32.  K advances in steps
+// of 16 BF16 through a 32 KB ring of LDS slots filled directly from global
+// memory in MFMA fragment order (see the staging notes below), so the loads
+// of the next steps are in flight while the matrix cores run the current one.
 #include "smx_device.h"
 #include "smx_internal.h"
 
@@ -20,6 +20,7 @@ namespace smx {
 
 typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
 typedef float f32x16_t __attribute__((ext_vector_type(16)));
+typedef float f32x4_t __attribute__((ext_vector_type(4)));
 
 constexpr int kGramThreads = 256;
 
@@ -102,36 +103,40 @@ int launch_gram_prep(const float *X, int64_t n, int64_t d, int64_t ldx, int64_t 
 // slot step s-1 used, and the MFMAs of step s run.
 //
 // WT = wave tile: the block tile is T = 2 WT, each wave owns WT / 32 x WT / 32
-// MFMA tiles.  T = 128 (WT = 64): 240 registers per lane and at most 64 KB of
-// LDS, so two blocks share a CU and one block's store-heavy epilogue overlaps
-// the other's MFMAs; measured on MI355X this beats T = 256 at one block per
-// CU, whose halved operand traffic does not bound the kernel.
+// MFMA tiles.  T = 128 (WT = 64) with a 32 KB ring (4 slots of 8 KB plain, 2
+// of 16 KB split): at most 128 registers per lane and 33 KB of LDS, so four
+// blocks share a CU and the store-heavy epilogue of one overlaps the others'
+// k loops.  Measured on MI355X against 2 blocks per CU with 64 KB rings and
+// against wider slots (2 or 4 k steps each, 32-64 KB): those were 4-20%
+// slower; so were persistent grids that overlap each tile's stores with the
+// next tile's k loop inside one block (design notes).
 template <bool SPLIT, int WT>
 struct GramCfg {
     static constexpr int NARR = SPLIT ? 4 : 2;     // A_hi, B_hi, (A_lo, B_lo)
     static constexpr int T = 2 * WT;               // block tile edge
     static constexpr int MT = WT / 32;             // MFMA tiles per wave edge
     static constexpr int RB = T / 32;              // 32-row blocks per panel
-    static constexpr int STAGE = NARR * RB;        // 1 KB blocks per stage
+    static constexpr int KS = 1;                   // 16-wide k blocks per stage
+    static constexpr int STAGE = NARR * RB * KS;   // 1 KB blocks per stage
     static constexpr int LPW = STAGE / 4;          // loads per wave per stage
-    static constexpr int S = SPLIT ? 4 : 8;        // ring depth (32 / 64 KB at T = 128)
+    static constexpr int S = SPLIT ? 2 : 4;         // ring depth: 32 KB either way
 };
 
 // One stage's loads into buf ([narr][rb_n][64] uint4); the counts are
 // compile-time constants at every (inlined) call.  Row blocks past the padded
 // operand (a ragged last tile) load its last block; their outputs are never
 // stored.
-__device__ __forceinline__ void gram_issue(uint4 *buf, int narr, int rb_n, const uint4 *__restrict__ hi,
+__device__ __forceinline__ void gram_issue(uint4 *buf, int narr, int rb_n, int ks, const uint4 *__restrict__ hi,
                                            const uint4 *__restrict__ lo, int64_t I0, int64_t J0, int64_t rbmax,
                                            int64_t KB, int64_t kb, int wave, int lane) {
 #pragma unroll
-    for (int t = 0; t < narr * rb_n / 4; ++t) {
-        const int gb = wave + 4 * t;  // 0 .. narr * rb_n - 1
-        const int arr = gb / rb_n, mb = gb % rb_n;
+    for (int t = 0; t < narr * rb_n * ks / 4; ++t) {
+        const int gb = wave + 4 * t;  // 0 .. narr * rb_n * ks - 1: [array][row block][k block]
+        const int arr = gb / (rb_n * ks), rem = gb % (rb_n * ks), mb = rem / ks, kk = rem % ks;
         const uint4 *src = (arr & 2) ? lo : hi;
         int64_t rb = (((arr & 1) ? J0 : I0) >> 5) + mb;
         rb = rb < rbmax ? rb : rbmax;
-        __builtin_amdgcn_global_load_lds(src + (rb * KB + kb) * 64 + lane, buf + gb * 64, 16, 0, 0);
+        __builtin_amdgcn_global_load_lds(src + (rb * KB + kb + kk) * 64 + lane, buf + gb * 64, 16, 0, 0);
     }
 }
 
@@ -176,7 +181,7 @@ __device__ __forceinline__ void lds_wait(bf16x8_t (&a)[NP][MT], bf16x8_t (&b)[NP
 // TILED: the tile-contiguous layout (tile (X, Y) at rank Y(Y+1)/2 + X times T^2,
 // element (i, j) at (i mod T) T + (j mod T), entries outside i <= j < n zero).
 template <int MAP, bool SPLIT, bool STATS, int WT, bool TILED>
-__global__ __launch_bounds__(kGramThreads) void edm_gram_kernel(MapGeom g, const uint16_t *__restrict__ hi,
+__global__ __launch_bounds__(kGramThreads, 4) void edm_gram_kernel(MapGeom g, const uint16_t *__restrict__ hi,
                                                                const uint16_t *__restrict__ lo,
                                                                const float *__restrict__ norms,
                                                                int64_t n, int64_t dpad,
@@ -188,7 +193,17 @@ __global__ __launch_bounds__(kGramThreads) void edm_gram_kernel(MapGeom g, const
     static_assert(S * BUF * 16 >= 4 * 32 * WT * 4, "the epilogue stages 32 rows per wave in the ring");
     uint64_t lin;
     int TX, TY;
-    if (!tile2_of<MAP, true>(g, lin, TX, TY)) return;
+    if (MAP == MAP_LAMBDA) {
+        // Pi2 column-major (w_y fastest), each XCD taking one contiguous range:
+        // the blocks an XCD runs at once hold consecutive tiles of one row panel,
+        // whose packed row segments are neighbours in D
+        lin = launch_index();
+        if (lin >= g.G) return;
+        if (!lambda2_cm(xcd_remap(uint32_t(lin), uint32_t(g.G)), g.lg, g.nb, TX, TY)) return;
+        if (SMX_CHECKED && !smx_check(0 <= TX && TX <= TY && TY < g.nb, kCheckMap)) return;
+    } else if (!tile2_of<MAP, true>(g, lin, TX, TY)) {
+        return;
+    }
     __shared__ __attribute__((aligned(16))) uint4 Lb[S * BUF];
     __shared__ __attribute__((aligned(16))) float nA[T], nB[T];
 
@@ -210,39 +225,52 @@ __global__ __launch_bounds__(kGramThreads) void edm_gram_kernel(MapGeom g, const
 #pragma unroll
             for (int e = 0; e < 16; ++e) acc[m][c][e] = 0.f;
 
-    const int nst = int(dpad / 16);  // 16-wide k steps
+    constexpr int KS = C::KS;
+    const int nst = int(dpad / (16 * KS));  // stages of KS 16-wide k blocks
     const int64_t KB = dpad / 16, rbmax = gram_rows(n) / 32 - 1;
     const uint4 *hi4 = reinterpret_cast<const uint4 *>(hi), *lo4 = reinterpret_cast<const uint4 *>(lo);
     for (int p = 0; p < S - 1 && p < nst; ++p)
-        gram_issue(Lb + p * BUF, C::NARR, C::RB, hi4, lo4, I0, J0, rbmax, KB, p, w, lane);
+        gram_issue(Lb + p * BUF, C::NARR, C::RB, KS, hi4, lo4, I0, J0, rbmax, KB, int64_t(p) * KS, w, lane);
     const uint32_t ring = lds_addr(Lb);
+    bf16x8_t a[2][NP][MT], b[2][NP][MT];  // [k block parity][hi, lo][sub-tile]
     for (int st = 0; st < nst; ++st) {
         const int ahead = nst - 1 - st < S - 2 ? nst - 1 - st : S - 2;
-        wait_vm_ahead<C::LPW, S - 2>(ahead);  // this wave's loads of step st have landed
-        __builtin_amdgcn_s_barrier();           // ... and every wave's; step st - 1 is consumed
+        wait_vm_ahead<C::LPW, S - 2>(ahead);  // this wave's loads of stage st have landed
+        __builtin_amdgcn_s_barrier();           // ... and every wave's; stage st - 1 is consumed
         if (st + S - 1 < nst)
-            gram_issue(Lb + ((st + S - 1) % S) * BUF, C::NARR, C::RB, hi4, lo4, I0, J0, rbmax, KB, st + S - 1, w,
-                       lane);
+            gram_issue(Lb + ((st + S - 1) % S) * BUF, C::NARR, C::RB, KS, hi4, lo4, I0, J0, rbmax, KB,
+                       int64_t(st + S - 1) * KS, w, lane);
         const uint32_t cur = ring + uint32_t((st % S) * BUF) * 16u + uint32_t(lane) * 16u;
-        bf16x8_t a[NP][MT], b[NP][MT];  // [hi, lo][sub-tile]
+        // k blocks of the stage, the fragments of block kk + 1 read while block kk multiplies
+        auto rd = [&](int kk, bf16x8_t(&fa)[NP][MT], bf16x8_t(&fb)[NP][MT]) {
 #pragma unroll
-        for (int p = 0; p < NP; ++p)
+            for (int p = 0; p < NP; ++p)
 #pragma unroll
-            for (int m = 0; m < MT; ++m) {
-                a[p][m] = lds_frag(cur + uint32_t(((2 * p) * C::RB + wm * MT + m) * 64 * 16));
-                b[p][m] = lds_frag(cur + uint32_t(((2 * p + 1) * C::RB + wn * MT + m) * 64 * 16));
-            }
-        lds_wait<NP, MT>(a, b);
-#pragma unroll
-        for (int m = 0; m < MT; ++m)
-#pragma unroll
-            for (int c = 0; c < MT; ++c) {
-                acc[m][c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[0][m], b[0][c], acc[m][c], 0, 0, 0);
-                if (SPLIT) {
-                    acc[m][c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[0][m], b[NP - 1][c], acc[m][c], 0, 0, 0);
-                    acc[m][c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[NP - 1][m], b[0][c], acc[m][c], 0, 0, 0);
+                for (int m = 0; m < MT; ++m) {
+                    fa[p][m] = lds_frag(cur + uint32_t((((2 * p) * C::RB + wm * MT + m) * KS + kk) * 64 * 16));
+                    fb[p][m] = lds_frag(cur + uint32_t((((2 * p + 1) * C::RB + wn * MT + m) * KS + kk) * 64 * 16));
                 }
-            }
+        };
+        rd(0, a[0], b[0]);
+        lds_wait<NP, MT>(a[0], b[0]);
+#pragma unroll
+        for (int kk = 0; kk < KS; ++kk) {
+            const int q = kk & 1;
+            if (kk + 1 < KS) rd(kk + 1, a[q ^ 1], b[q ^ 1]);
+#pragma unroll
+            for (int m = 0; m < MT; ++m)
+#pragma unroll
+                for (int c = 0; c < MT; ++c) {
+                    acc[m][c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[q][0][m], b[q][0][c], acc[m][c], 0, 0, 0);
+                    if (SPLIT) {
+                        acc[m][c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[q][0][m], b[q][NP - 1][c], acc[m][c], 0,
+                                                                            0, 0);
+                        acc[m][c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[q][NP - 1][m], b[q][0][c], acc[m][c], 0,
+                                                                            0, 0);
+                    }
+                }
+            if (kk + 1 < KS) lds_wait<NP, MT>(a[q ^ 1], b[q ^ 1]);
+        }
     }
 
     // Epilogue.  32 x 32 accumulator layout: lane l, element e holds row
@@ -316,6 +344,7 @@ __global__ __launch_bounds__(kGramThreads) void edm_gram_kernel(MapGeom g, const
         if (t == 0) stats_add(slots, lin, c, h);
     }
 }
+
 
 template <int MAP, bool SPLIT, int WT, bool TILED>
 static void go_gram(const MapGeom &g, const uint16_t *hi, const uint16_t *lo, const float *norms,

@@ -83,6 +83,24 @@ SMX_HD bool lambda2(uint32_t id, int lg, int nb, int &X, int &Y) {
     return y < uint32_t(nb);  // x <= y
 }
 
+// The same parallel space Pi2 enumerated with w_y fastest ("column-major"):
+// ids [0, (nb'/2) nb') are (w_x, w_y) = (id >> lg, id mod nb'), w_y = 0 the
+// first diagonal row; the last nb'/2 ids are the row w_y = nb'.  lambda2 itself
+// is unchanged.  Consecutive ids of one level (w_y in [b, 2b)) map to
+// consecutive Y at a fixed X: a strip of tiles along one row panel.
+SMX_HD uint32_t lambda2_cm_to_xfast(uint32_t id, int lg) {
+    if (lg == 0) return id;
+    const int h = lg - 1;
+    const uint32_t body = 1u << (h + lg);
+    const uint32_t wx = id < body ? id >> lg : id - body;
+    const uint32_t wy = id < body ? id & ((1u << lg) - 1u) : 1u << lg;
+    return (wy << h) | wx;
+}
+
+SMX_HD bool lambda2_cm(uint32_t id, int lg, int nb, int &X, int &Y) {
+    return lambda2(lambda2_cm_to_xfast(id, lg), lg, nb, X, Y);
+}
+
 // ---------------------------------------------------------------- lambda3
 // Sec. III-C, two recursion branches.  Pi3 = (nb'/2) x (nb'/2) x (nb'/2 + nb'/4),
 // linearised x fastest.  Target of Pi3: {X <= Y < Z}.  The first nb'/2
