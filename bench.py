@@ -38,7 +38,7 @@ LJ_FLOPS = 30                              # declared flops per pair (fwd + bwd)
 # rocprofv3 PMC passes (FETCH_SIZE, WRITE_SIZE, scaled by a 1 GiB copy) recorded
 # in profiles/step_lambda_hbm_traffic_pmc.md.  They describe the kernel built
 # from sources with this hash; once those change the figure is reported as null.
-AT_TRAFFIC = {"src_sha16": "cb926d0ae62e874b", "fetch_bytes": 0.000944e9, "write_bytes": 19.645e9,
+AT_TRAFFIC = {"src_sha16": "be8079101ea2926e", "fetch_bytes": 0.000944e9, "write_bytes": 19.645e9,
               "valu_instructions": 39611332864}  # SQ_INSTS_VALU (wave instructions) per launch
 # single-issue FP32 vector rate: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
 VALU_ISSUE_SPEC = 256 * 4 * 16 * 2.4e9
@@ -62,8 +62,8 @@ def parse():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-compare", action="store_true")
     p.add_argument("--quick-compare", action="store_true",
-                   help="compare lambda with the bounding box only (no linear / recursive maps, no map-only "
-                        "parallel spaces): a short run for tracing")
+                   help="compare lambda with the bounding box only (no linear / recursive maps; map-only "
+                        "parallel spaces of these two): a short run for tracing")
     p.add_argument("--only", default="", help="comma list of edm,gram,at (default all)")
     p.add_argument("--calibrate-copy", action="store_true",
                    help="first run one 1 GiB device-to-device copy (known traffic) to scale "
@@ -445,7 +445,8 @@ def main():
         # count, so the time is the map plus the launched blocks alone.
         mo = {}
         log("map-only parallel spaces")
-        for kind in () if args.quick_compare else ("lambda", "bbox", "linear", "lambda_below", "recursive", "recursive_launch"):
+        for kind in QUICK_MAPS if args.quick_compare else ("lambda", "bbox", "linear", "lambda_below", "recursive",
+                                                          "recursive_launch"):
             for m, n, rho in ((2, N_EDM, 16), (3, N_AT, 8), (4, N_MAP4, 8)):
                 if m == 4 and kind == "lambda_below":
                     continue  # not defined for the 4-simplex
