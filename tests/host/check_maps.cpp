@@ -2,7 +2,9 @@
 // kernels use), for running under AddressSanitizer and UndefinedBehaviorSanitizer:
 // every block of every map is decoded for a range of nb, and the mapped tiles
 // must cover the target simplex exactly once (and the lambda inverses must
-// return each block), with no shift, overflow or out-of-range access.  Exit status 0 and "ok" on success.
+// return each block), with no shift, overflow or out-of-range access.  The
+// column-major enumeration of Pi2 and the XCD renumbering must be permutations
+// of their ranges.  Exit status 0 and "ok" on success.
 #include <cstdio>
 #include <cstdlib>
 #include <vector>
@@ -91,7 +93,47 @@ static void check(int m, int nb, int map) {
         std::printf("m=%d nb=%d map=%d: %lld of %lld tiles mapped\n", m, nb, map, mapped, target);
 }
 
+// lambda2 through the column-major enumeration of Pi2, after the XCD
+// renumbering (the Gram kernel's composition): each id in [0, G) reaches a
+// distinct Pi2 point, and the mapped tiles cover the nb(nb+1)/2 tiles once.
+static void check_cm(int nb) {
+    const int lg = ceil_log2_u64(uint64_t(nb));
+    const uint32_t G = lambda2_blocks(lg);
+    std::vector<unsigned char> hit(G, 0), seen(size_t(binom(nb + 1, 2)), 0);
+    long long mapped = 0;
+    for (uint32_t id = 0; id < G; ++id) {
+        const uint32_t r = xcd_remap(id, G);
+        const uint32_t xf = r < G ? lambda2_cm_to_xfast(r, lg) : G;
+        if (xf >= G || hit[xf]++) {
+            if (fails++ < 10) std::printf("cm nb=%d: id %u is not a permutation\n", nb, id);
+            continue;
+        }
+        int x = 0, y = 0;
+        if (!lambda2_cm(r, lg, nb, x, y)) continue;
+        if (x < 0 || y < x || y >= nb) {
+            if (fails++ < 10) std::printf("cm nb=%d: id %u tile out of the simplex\n", nb, id);
+            continue;
+        }
+        const int t[2] = {x, y};
+        if (seen[size_t(rank_tuple(t, 2))]++ && fails++ < 10) std::printf("cm nb=%d: tile mapped twice\n", nb);
+        ++mapped;
+    }
+    if (mapped != binom(nb + 1, 2) && fails++ < 10) std::printf("cm nb=%d: %lld tiles mapped\n", nb, mapped);
+}
+
+// the XCD renumbering is a bijection on [0, G) for every G, including G < 8
+static void check_xcd(uint32_t G) {
+    std::vector<unsigned char> hit(G, 0);
+    for (uint32_t b = 0; b < G; ++b) {
+        const uint32_t r = xcd_remap(b, G);
+        if ((r >= G || hit[r]++) && fails++ < 10) std::printf("xcd G=%u: %u -> %u\n", G, b, r);
+    }
+}
+
 int main() {
+    for (int nb = 1; nb <= 300; nb += (nb < 40 ? 1 : 37)) check_cm(nb);
+    for (uint32_t G = 1; G <= 200; ++G) check_xcd(G);
+    check_xcd(8191u * 4097u);
     const int maps2[] = {MAP_LAMBDA, MAP_LINEAR, MAP_BELOW, MAP_REC};
     for (int nb = 1; nb <= 300; nb += (nb < 40 ? 1 : 37))
         for (int map : maps2) check(2, nb, map);
