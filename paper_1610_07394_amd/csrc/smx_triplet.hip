@@ -89,7 +89,10 @@ __global__ __launch_bounds__(kTripThreads, 3) void at_kernel(MapGeom g, const fl
                                                           int64_t ldx, float nu, double *__restrict__ G64,
                                                           double *__restrict__ eslots,
                                                           unsigned long long *sslots) {
-    constexpr int PS = kTripTile * kTripLd;
+    // Plane stride: 16 floats of padding put consecutive planes 16 of the 32 LDS
+    // banks apart, so the two half-wave weight planes that one store of the k
+    // loop writes (lanes 0-15 and 16-31 at the same offsets) share no bank.
+    constexpr int PS = kTripTile * kTripLd + 16;
     // LDS planes of PS floats.  Pair sets: ij (rows i, cols j), ki (rows k,
     // cols i), kj (rows k, cols j).
     //   GRAD:  0 s_ki, 1 s_kj, 2 m4_ki, 3 m4_kj, 4 d5_ki, 5 d5_kj (m4 = -4 s);
@@ -325,9 +328,14 @@ __global__ __launch_bounds__(kTripThreads, 3) void at_kernel(MapGeom g, const fl
             }
             const double eb = block_sum<double, kTripThreads>(double(e), red);  // synchronises the block
             if (t == 0) atomicAdd(eslots + (lin % kSlots) * kSlotStride + 0, eb * (-double(nu) / 12.0));
-            // transposes: W_ji [j][i] -> 3, W_ik [i][k] -> 7, W_jk [j][k] -> 9
-            for (int o = t; o < kTripTile * kTripTile; o += kTripThreads) {
-                const int r = o >> 5, c = o & 31, x = r * kTripLd + c, xt = c * kTripLd + r;
+            // transposes: W_ji [j][i] -> 3, W_ik [i][k] -> 7, W_jk [j][k] -> 9.  A
+            // half-wave takes one diagonal d of the plane, lane r the element
+            // (r, (r + d) mod 32): the banks of the read (5 r + d) and of the
+            // transposed store (5 r + 4 d, mod 32) are distinct across its 32 lanes.
+#pragma unroll
+            for (int m = 0; m < 4; ++m) {
+                const int r = t & 31, c = (r + (t >> 5) + 8 * m) & 31;
+                const int x = r * kTripLd + c, xt = c * kTripLd + r;
                 plane(3)[xt] = plane(2)[x];
                 plane(W_IK + 1)[xt] = plane(W_IK)[x];
                 plane(W_JK + 1)[xt] = plane(W_JK)[x];
