@@ -397,7 +397,9 @@ def main():
                 "traffic": None if traffic is None else traffic[0] + traffic[1],
                 "traffic_fetch_bytes": None if traffic is None else traffic[0],
                 "traffic_write_bytes": None if traffic is None else traffic[1],
-                "per_unit": "80 flops per triplet (20 forward + 60 backward), 9.159e10 triplets per launch"}
+                "per_unit": "80 flops per triplet (20 forward + 60 backward), 9.159e10 triplets per launch",
+                "frac_basis": "declared flops against the packed-FP32 vector peak; the kernel is built without "
+                              "packed FP32, so its physical ceiling is the VALU issue rate (valu_issue)"}
         if traffic is not None:
             issue = traffic[2] * 64 / t  # VALU lane-instructions per second
             ceil = valu_ceiling(smx, torch, dev)

@@ -30,10 +30,17 @@
 // triplet only adds three scalars.
 //
 // Block: 256 threads own the 32^3 triplets of tile (X, Y, Z), X <= Y <= Z, one
-// tile after another: the grid is persistent (kAtPersistBlocks blocks, block b
-// taking logical ids b, b + grid, ...), and each tile's positions are loaded
-// while the previous tile's triplets run, so a block no longer starts with a
-// global load (the kernel took 64-65 ms with one block per tile, 55 ms so).
+// tile after another: the grid is persistent (at most kAtPersistBlocks blocks),
+// the logical ids are dealt out in groups of R = 2^r consecutive ids (block b
+// taking groups b, b + grid, ...: every block samples the whole parallel space,
+// so blocks take equal time), and each tile's positions are loaded while the
+// previous tile's triplets run, so a block no longer starts with a global load
+// (the kernel took 64-65 ms with one block per tile, 55 ms so).  Consecutive
+// ids of every map here move one tile index and keep the other two (lambda3
+// walks w_x fastest: a Pi3 row changes X on one side of its fold and Z on the
+// other; the bounding box and the linear listing change X), so inside a group
+// a particle tile's forces are summed in registers while its index stays and
+// go to the gradient once when it changes.
 //   1. positions of the three 32-particle tiles -> LDS;
 //   2. the 3 x 32 x 32 pair terms s, -4 s, d^5 -> LDS; d^5 = 0 for a pair that
 //      is out of order (i >= j, j >= k, i >= k) or past n, which zeroes R for
@@ -88,7 +95,7 @@ template <int MAP, bool GRAD, bool STATS>
 __global__ __launch_bounds__(kTripThreads, 3) void at_kernel(MapGeom g, const float *__restrict__ Xp, int64_t n,
                                                           int64_t ldx, float nu, double *__restrict__ G64,
                                                           double *__restrict__ eslots,
-                                                          unsigned long long *sslots) {
+                                                          unsigned long long *sslots, int grp_lg) {
     // Plane stride: 16 floats of padding put consecutive planes 16 of the 32 LDS
     // banks apart, so the two half-wave weight planes that one store of the k
     // loop writes (lanes 0-15 and 16-31 at the same offsets) share no bank.
@@ -112,15 +119,23 @@ __global__ __launch_bounds__(kTripThreads, 3) void at_kernel(MapGeom g, const fl
     auto plane = [&](int i) -> float * { return L + i * PS; };
 
     const int t = threadIdx.x;
-    // persistent blocks: block b takes logical ids b, b + nblk, ...; the next
-    // tile's positions are loaded while the current tile's triplets run
-    const uint64_t nblk = uint64_t(gridDim.x) * gridDim.y;
-    uint64_t id = uint64_t(blockIdx.y) * gridDim.x + blockIdx.x;
+    // persistent blocks: block b takes the ids of groups b, b + nblk, ... in
+    // order; the next tile's positions are loaded while the current tile's
+    // triplets run
+    const uint64_t nblk = uint64_t(gridDim.x) * gridDim.y, R = uint64_t(1) << grp_lg;
+    uint64_t id = (uint64_t(blockIdx.y) * gridDim.x + blockIdx.x) << grp_lg;
+    auto advance = [&](uint64_t i) -> uint64_t {  // the block's next id
+        ++i;
+        return (i & (R - 1)) ? i : i + (nblk - 1) * R;
+    };
     auto next_valid = [&](uint64_t &i, uint64_t &l, int &x, int &y, int &z) -> bool {
-        for (; i < g.G; i += nblk)
+        for (; i < g.G; i = advance(i))
             if (tile3_of_id<MAP>(g, uint32_t(i), l, x, y, z)) return true;
         return false;
     };
+    // forces on the particles of this wave's tile role (wave 0 X, 1 Y, 2 Z),
+    // lanes 0-31, summed while the role's tile index stays (FP64)
+    double fx = 0.0, fy = 0.0, fz = 0.0;
     auto load_pos = [&](int x, int y, int z) {
         float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
         if (t < 3 * kTripTile) {
@@ -142,7 +157,7 @@ __global__ __launch_bounds__(kTripThreads, 3) void at_kernel(MapGeom g, const fl
         const int64_t base[3] = {int64_t(TX) * kTripTile, int64_t(TY) * kTripTile, int64_t(TZ) * kTripTile};
         if (t < 3 * kTripTile) Pos[t >> 5][t & 31] = pv;
         __syncthreads();
-        uint64_t nid = id + nblk, nlin = 0;
+        uint64_t nid = advance(id), nlin = 0;
         int NX = 0, NY = 0, NZ = 0;
         const bool more = next_valid(nid, nlin, NX, NY, NZ);
         const float4 pnext = more ? load_pos(NX, NY, NZ) : make_float4(0.f, 0.f, 0.f, 0.f);
@@ -372,13 +387,21 @@ __global__ __launch_bounds__(kTripThreads, 3) void at_kernel(MapGeom g, const fl
                 gx += __shfl_xor(gx, 32, kWave);
                 gy += __shfl_xor(gy, 32, kWave);
                 gz += __shfl_xor(gz, 32, kWave);
-                const int64_t gp = base[tile] + a;
-                if (h == 0 && gp < n) {
-                    // W is 3/8 of the accumulated sums
-                    const double sc = 0.75 * double(nu);
-                    atomicAdd(G64 + 3 * gp + 0, sc * double(gx));
-                    atomicAdd(G64 + 3 * gp + 1, sc * double(gy));
-                    atomicAdd(G64 + 3 * gp + 2, sc * double(gz));
+                // W is 3/8 of the accumulated sums
+                const double sc = 0.75 * double(nu);
+                fx += sc * double(gx);
+                fy += sc * double(gy);
+                fz += sc * double(gz);
+                const int cur = tile == 0 ? TX : (tile == 1 ? TY : TZ);
+                const int nxt = !more ? -1 : (tile == 0 ? NX : (tile == 1 ? NY : NZ));
+                if (cur != nxt) {  // the role's tile changes: its forces go to the gradient
+                    const int64_t gp = base[tile] + a;
+                    if (h == 0 && gp < n) {
+                        atomicAdd(G64 + 3 * gp + 0, fx);
+                        atomicAdd(G64 + 3 * gp + 1, fy);
+                        atomicAdd(G64 + 3 * gp + 2, fz);
+                    }
+                    fx = fy = fz = 0.0;
                 }
             }
         }
@@ -393,17 +416,27 @@ __global__ __launch_bounds__(kTripThreads, 3) void at_kernel(MapGeom g, const fl
     }
 }
 
+// Group size R = 2^r of the persistent kernel: the largest R <= 32 that still
+// leaves every block of a full grid at least one group.
+static int at_group_lg(uint64_t G) {
+    int r = 0;
+    while (r < 5 && (G >> (r + 1)) >= uint64_t(kAtPersistBlocks)) ++r;
+    return r;
+}
+
 template <int MAP, bool GRAD>
 static void go_at(const MapGeom &g, const float *X, int64_t n, int64_t ldx, float nu, double *G64,
                   double *eslots, unsigned long long *sslots, hipStream_t s) {
-    const uint64_t nblk = g.G < uint64_t(kAtPersistBlocks) ? g.G : uint64_t(kAtPersistBlocks);
+    const int r = at_group_lg(g.G);
+    const uint64_t groups = (g.G + (uint64_t(1) << r) - 1) >> r;
+    const uint64_t nblk = groups < uint64_t(kAtPersistBlocks) ? groups : uint64_t(kAtPersistBlocks);
     const dim3 grid(uint32_t(nblk > 0 ? nblk : 1));
     if (sslots)
         hipLaunchKernelGGL((at_kernel<MAP, GRAD, true>), grid, dim3(kTripThreads), 0, s, g, X, n, ldx, nu,
-                           G64, eslots, sslots);
+                           G64, eslots, sslots, r);
     else
         hipLaunchKernelGGL((at_kernel<MAP, GRAD, false>), grid, dim3(kTripThreads), 0, s, g, X, n, ldx, nu,
-                           G64, eslots, sslots);
+                           G64, eslots, sslots, r);
 }
 
 int launch_triplet(const MapGeom &g, const float *X, int64_t n, int64_t ldx, float nu, bool grad,
