@@ -33,9 +33,10 @@
 // tile after another: the grid is persistent (at most kAtPersistBlocks blocks),
 // the logical ids are dealt out in groups of R = 2^r consecutive ids (block b
 // taking groups b, b + grid, ...: every block samples the whole parallel space,
-// so blocks take equal time), and each tile's positions are loaded while the
-// previous tile's triplets run, so a block no longer starts with a global load
-// (the kernel took 64-65 ms with one block per tile, 55 ms so).  Consecutive
+// so blocks take equal time; R = 1 for the maps with many empty ids), and each
+// tile's positions are loaded while the previous tile's triplets run, so a
+// block no longer starts with a global load (the kernel took 64-65 ms with one
+// block per tile, 55 ms so).  Consecutive
 // ids of every map here move one tile index and keep the other two (lambda3
 // walks w_x fastest: a Pi3 row changes X on one side of its fold and Z on the
 // other; the bounding box and the linear listing change X), so inside a group
@@ -67,9 +68,11 @@
 namespace smx {
 
 constexpr int kTripThreads = 256;
-// persistent grid of the triplet kernels: 32 blocks per resident block slot
-// (256 CUs x 3 blocks); measured flat from 16 to 128
-constexpr int kAtPersistBlocks = 256 * 3 * 32;
+// persistent grid of the triplet kernels: about 32 blocks per resident block
+// slot (256 CUs x 3 blocks; measured flat from 16 to 128), and a prime, so that
+// a block's groups b, b + grid, ... do not keep to one position of the parallel
+// space's rows (which are powers of two or nb long).
+constexpr int kAtPersistBlocks = 24571;
 constexpr int kTripLd = kTripTile + 4;  // LDS row stride (floats)
 
 // DPP lane moves (all 64 lanes active): quad_perm xor 1 / xor 2 and
@@ -417,8 +420,14 @@ __global__ __launch_bounds__(kTripThreads, 3) void at_kernel(MapGeom g, const fl
 }
 
 // Group size R = 2^r of the persistent kernel: the largest R <= 32 that still
-// leaves every block of a full grid at least one group.
-static int at_group_lg(uint64_t G) {
+// leaves every block of a full grid at least one group, for the maps whose ids
+// nearly all decode to tiles (lambda, the linear listing).  The other maps deal
+// single ids: five in six bounding-box ids decode to no tile, and with groups of
+// 32 a block's tile count ranged from 0 to 1.8x the mean (the launch took 2.1x
+// the time with a grid of 256 * 3 * 32 blocks, whose groups kept each block to
+// the same 32 X tiles).
+static int at_group_lg(uint64_t G, int map) {
+    if (map != MAP_LAMBDA && map != MAP_LINEAR) return 0;
     int r = 0;
     while (r < 5 && (G >> (r + 1)) >= uint64_t(kAtPersistBlocks)) ++r;
     return r;
@@ -427,7 +436,7 @@ static int at_group_lg(uint64_t G) {
 template <int MAP, bool GRAD>
 static void go_at(const MapGeom &g, const float *X, int64_t n, int64_t ldx, float nu, double *G64,
                   double *eslots, unsigned long long *sslots, hipStream_t s) {
-    const int r = at_group_lg(g.G);
+    const int r = at_group_lg(g.G, MAP);
     const uint64_t groups = (g.G + (uint64_t(1) << r) - 1) >> r;
     const uint64_t nblk = groups < uint64_t(kAtPersistBlocks) ? groups : uint64_t(kAtPersistBlocks);
     const dim3 grid(uint32_t(nblk > 0 ? nblk : 1));
