@@ -420,14 +420,15 @@ __global__ __launch_bounds__(kTripThreads, 3) void at_kernel(MapGeom g, const fl
 }
 
 // Group size R = 2^r of the persistent kernel: the largest R <= 32 that still
-// leaves every block of a full grid at least one group, for the maps whose ids
-// nearly all decode to tiles (lambda, the linear listing).  The other maps deal
-// single ids: five in six bounding-box ids decode to no tile, and with groups of
-// 32 a block's tile count ranged from 0 to 1.8x the mean (the launch took 2.1x
-// the time with a grid of 256 * 3 * 32 blocks, whose groups kept each block to
-// the same 32 X tiles).
-static int at_group_lg(uint64_t G, int map) {
-    if (map != MAP_LAMBDA && map != MAP_LINEAR) return 0;
+// leaves every block of a full grid at least one group, for the gradient (the
+// groups exist for its force sums) on the maps whose ids nearly all decode to
+// tiles (lambda, the linear listing).  The other maps deal single ids: five in
+// six bounding-box ids decode to no tile, and with groups of 32 a block's tile
+// count ranged from 0 to 1.8x the mean (the launch took 2.1x the time with a
+// grid of 256 * 3 * 32 blocks, whose groups kept each block to the same 32 X
+// tiles).
+static int at_group_lg(uint64_t G, int map, bool grad) {
+    if (!grad || (map != MAP_LAMBDA && map != MAP_LINEAR)) return 0;
     int r = 0;
     while (r < 5 && (G >> (r + 1)) >= uint64_t(kAtPersistBlocks)) ++r;
     return r;
@@ -436,7 +437,7 @@ static int at_group_lg(uint64_t G, int map) {
 template <int MAP, bool GRAD>
 static void go_at(const MapGeom &g, const float *X, int64_t n, int64_t ldx, float nu, double *G64,
                   double *eslots, unsigned long long *sslots, hipStream_t s) {
-    const int r = at_group_lg(g.G, MAP);
+    const int r = at_group_lg(g.G, MAP, GRAD);
     const uint64_t groups = (g.G + (uint64_t(1) << r) - 1) >> r;
     const uint64_t nblk = groups < uint64_t(kAtPersistBlocks) ? groups : uint64_t(kAtPersistBlocks);
     const dim3 grid(uint32_t(nblk > 0 ? nblk : 1));
