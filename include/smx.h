@@ -247,7 +247,9 @@ int smx_simplex_count(int m, int64_t n, int rho, int map, int strict, int64_t *d
 int smx_edm_packed(const float *d_X, int64_t n, int64_t d, int64_t ldx, int map, int prec,
                    float *d_D, void *d_ws, size_t ws_bytes, int64_t *d_stats, void *stream);
 
-/* The same squared distances in a tile-contiguous layout: 128 x 128 tiles for
+/* Diagnostic of the store ceiling (the path's output is smx_edm_packed's): it
+ * separates the cost of the packed layout from the kernel's.
+ * The same squared distances in a tile-contiguous layout: 128 x 128 tiles for
  * every precision, nb = ceil(n / 128), d_D of nb(nb+1)/2 * 16384 floats; tile
  * (X, Y), X <= Y < nb, starts at (Y(Y+1)/2 + X) * 16384 and element (i, j) sits at
  * 128 (i mod 128) + (j mod 128) of tile (i/128, j/128); entries of a tile that
@@ -319,7 +321,9 @@ int smx_triplet_energy_grad_noalloc(const float *d_X, int64_t n, int64_t ldx, co
 int smx_triplet_packed(const float *d_X, int64_t n, int64_t ldx, double nu, int map, float *d_E, void *d_ws,
                        size_t ws_bytes, int64_t *d_stats, void *stream);
 
-/* The same per-triplet energies in a tile-contiguous layout, so that each
+/* Diagnostic of the store ceiling (the path's output is smx_triplet_packed's):
+ * it separates the cost of the packed layout from the kernel's.
+ * The same per-triplet energies in a tile-contiguous layout, so that each
  * 32^3 tile is written as one contiguous 128 KB run.  With nb = ceil(n / 32),
  * d_E holds C(nb+2, 3) * 32768 floats: tile (X, Y, Z), X <= Y <= Z < nb, starts
  * at rank * 32768 with rank = Z(Z+1)(Z+2)/6 + Y(Y+1)/2 + X, and triplet (i, j, k)

@@ -191,6 +191,25 @@ def test_at_n2048_full_gradient():
     assert int(s[0]) == g["volume"] and int(s[1]) % (1 << 64) == int(g["checksum"])
 
 
+def test_at_grad_id_groups_n3000():
+    """n = 3000 (nb = 94, lambda3's parallel space at nb' = 128): the gradient
+    kernel deals lambda's logical ids in groups of 16 and the linear listing's in
+    groups of 4, summing a particle tile's forces across the tiles of a group;
+    the bounding box deals single ids.  Energy and every gradient row against the
+    oracle."""
+    X = _pts(3000, seed=30)
+    Xt = _gpu(X)
+    e_ref = oracle.at_energy(X)
+    g_ref = oracle.at_grad(X)
+    for kind in ("lambda", "linear", "bbox"):
+        E, G = smx.triplet_energy_grad(Xt, AT, kind)
+        torch.cuda.synchronize()
+        rel = abs(E[0].item() - e_ref) / abs(e_ref)
+        err = _fmetric(G.cpu().numpy().astype(np.float64), g_ref)
+        print(f"  n=3000 {kind}: energy rel {rel:.2e}, grad {err:.2e}", flush=True)
+        assert rel <= 1e-5 and err <= 1e-5
+
+
 def test_at_lj_n8192_full_size():
     """The n = 8192 workload (9.2e10 triplets + 3.4e7 pairs): energies and the
     whole gradient, all 8192 rows, against the oracle's FP64 values (stored by
