@@ -22,8 +22,8 @@
 // after the loop.  E_t is homogeneous of
 // degree -9/2 in the pair terms, so (Euler) sum_p s_p dE_t/ds_p = -9/2 E_t:
 // the energy is read off the same sums, E_t = -(nu / 12) R sum_p x_p with
-// x_p = s_p (K - 4 u s_p) - Q.  About 24 FP32 operations per triplet give the
-// energy and all three weights.
+// x_p = s_p (K - 4 u s_p) - Q.  About 22 FP32 operations per triplet give the
+// energy and all three weights (8 P from a register copy of 2 s_ij).
 // The gradient never forms per-particle forces per triplet.  Because E depends
 // on positions only through the pair terms, dE/dx_a = sum_b 2 W_ab (x_a - x_b)
 // with W_ab = sum over triplets holding the pair {a, b} of dE_t/ds_ab.  So each
@@ -208,7 +208,7 @@ __global__ __launch_bounds__(kTripThreads, 3) void at_kernel(MapGeom g, const fl
         const int lane = t & 63, row = lane >> 4, q = (lane >> 2) & 3, el = lane & 3;
         const int kb = __builtin_amdgcn_readfirstlane(t >> 6);  // wave index
         const int ib = 4 * (row >> 1) + q, jb = 4 * (row & 1) + el;
-        float s1[4][4], f1[4][4], w1[4][4];
+        float s1[4][4], f1[4][4], w1[4][4], s1x2[4][4];
 #pragma unroll
         for (int a = 0; a < 4; ++a) {
             const int o = (4 * ib + a) * kTripLd + 4 * jb;
@@ -217,7 +217,10 @@ __global__ __launch_bounds__(kTripThreads, 3) void at_kernel(MapGeom g, const fl
             s1[a][0] = sv.x; s1[a][1] = sv.y; s1[a][2] = sv.z; s1[a][3] = sv.w;
             f1[a][0] = fv.x; f1[a][1] = fv.y; f1[a][2] = fv.z; f1[a][3] = fv.w;
 #pragma unroll
-            for (int b = 0; b < 4; ++b) w1[a][b] = 0.f;
+            for (int b = 0; b < 4; ++b) {
+                w1[a][b] = 0.f;
+                s1x2[a][b] = s1[a][b] + s1[a][b];
+            }
         }
         // the (i, j) planes become the per-k weight planes
         if (GRAD) __syncthreads();
@@ -256,13 +259,13 @@ __global__ __launch_bounds__(kTripThreads, 3) void at_kernel(MapGeom g, const fl
                     const float q4 = -(m2a[b] * sc);            // 4 s2 s3
                     const float gg = __builtin_fmaf(-t2n, t2n, q4);  // g
                     const float y = u * gg;
-                    const float P4 = sa * q4;                   // 4 P
+                    const float P8 = s1x2[a][b] * q4;           // 8 P
                     const float R = f1[a][b] * (f2a[b] * f3a[a]);
                     if (!GRAD) {
                         // 4 (P - 3/8 T) = 3/2 u g - 8 P
-                        e = __builtin_fmaf(__builtin_fmaf(1.5f, y, -2.f * P4), R, e);
+                        e = __builtin_fmaf(__builtin_fmaf(1.5f, y, -P8), R, e);
                     } else {
-                        const float nQ = __builtin_fmaf(2.f, P4, -2.5f * y);  // -Q
+                        const float nQ = __builtin_fmaf(-2.5f, y, P8);  // -Q = 8 P - 5/2 u g
                         const float tu = u + u;
                         const float K = __builtin_fmaf(tu, u, gg);
                         // s_p (K - 4 u s_p) - Q;  K - 4 u s_1 = g - 2 u t2
