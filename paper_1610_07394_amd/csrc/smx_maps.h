@@ -101,6 +101,23 @@ SMX_HD bool lambda2_cm(uint32_t id, int lg, int nb, int &X, int &Y) {
     return lambda2(lambda2_cm_to_xfast(id, lg), lg, nb, X, Y);
 }
 
+// Pi2 in patches of 2^pxl (w_x) x 2^pyl (w_y) ids (clamped to nb'/2 x nb'),
+// w_y fastest inside a patch, the patches with their w_y index fastest; the
+// row w_y = nb' comes last.  Inside one level a patch of Pi2 is a patch of
+// tiles of one cross square (X = w_x + q b, Y = w_y + 2 q b), so consecutive
+// ids reuse 2^pxl row panels and 2^pyl column panels.
+SMX_HD uint32_t lambda2_patch_to_xfast(uint32_t id, int lg, int pxl, int pyl) {
+    if (lg == 0) return id;
+    const int h = lg - 1;
+    const uint32_t body = 1u << (h + lg);
+    if (id >= body) return (1u << (h + lg)) | (id - body);
+    const int px = pxl < h ? pxl : h, py = pyl < lg ? pyl : lg;
+    const uint32_t p = id >> (px + py), r = id & ((1u << (px + py)) - 1u);
+    const uint32_t pwy = p & ((1u << (lg - py)) - 1u), pwx = p >> (lg - py);
+    const uint32_t wy = (pwy << py) | (r & ((1u << py) - 1u)), wx = (pwx << px) | (r >> py);
+    return (wy << h) | wx;
+}
+
 // ---------------------------------------------------------------- lambda3
 // Sec. III-C, two recursion branches.  Pi3 = (nb'/2) x (nb'/2) x (nb'/2 + nb'/4),
 // linearised x fastest.  Target of Pi3: {X <= Y < Z}.  The first nb'/2

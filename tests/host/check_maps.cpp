@@ -3,8 +3,8 @@
 // every block of every map is decoded for a range of nb, and the mapped tiles
 // must cover the target simplex exactly once (and the lambda inverses must
 // return each block), with no shift, overflow or out-of-range access.  The
-// column-major enumeration of Pi2 and the XCD renumbering must be permutations
-// of their ranges.  Exit status 0 and "ok" on success.
+// column-major and patch enumerations of Pi2 and the XCD renumbering must be
+// permutations of their ranges.  Exit status 0 and "ok" on success.
 #include <cstdio>
 #include <cstdlib>
 #include <vector>
@@ -121,6 +121,20 @@ static void check_cm(int nb) {
     if (mapped != binom(nb + 1, 2) && fails++ < 10) std::printf("cm nb=%d: %lld tiles mapped\n", nb, mapped);
 }
 
+// the patch enumeration of Pi2 is a permutation of its ids for every patch shape
+static void check_patch(int lg) {
+    const uint32_t G = lambda2_blocks(lg);
+    for (int pxl = 0; pxl <= 6; ++pxl)
+        for (int pyl = 0; pyl <= 6; ++pyl) {
+            std::vector<unsigned char> hit(G, 0);
+            for (uint32_t id = 0; id < G; ++id) {
+                const uint32_t xf = lambda2_patch_to_xfast(id, lg, pxl, pyl);
+                if ((xf >= G || hit[xf]++) && fails++ < 10)
+                    std::printf("patch lg=%d %dx%d: id %u -> %u\n", lg, pxl, pyl, id, xf);
+            }
+        }
+}
+
 // the XCD renumbering is a bijection on [0, G) for every G, including G < 8
 static void check_xcd(uint32_t G) {
     std::vector<unsigned char> hit(G, 0);
@@ -133,6 +147,7 @@ static void check_xcd(uint32_t G) {
 int main() {
     for (int nb = 1; nb <= 300; nb += (nb < 40 ? 1 : 37)) check_cm(nb);
     for (uint32_t G = 1; G <= 200; ++G) check_xcd(G);
+    for (int lg = 0; lg <= 10; ++lg) check_patch(lg);
     check_xcd(8191u * 4097u);
     const int maps2[] = {MAP_LAMBDA, MAP_LINEAR, MAP_BELOW, MAP_REC};
     for (int nb = 1; nb <= 300; nb += (nb < 40 ? 1 : 37))
