@@ -73,6 +73,10 @@ constexpr int kTripThreads = 256;
 // a block's groups b, b + grid, ... do not keep to one position of the parallel
 // space's rows (which are powers of two or nb long).
 constexpr int kAtPersistBlocks = 24571;
+// grid cap of the launches that deal groups of 32 (the largest ones: about one
+// group per block, 128 blocks per slot, also a prime): 53.3 -> 52.7 ms at
+// n = 8192 against 24571 blocks; smaller launches keep the cap above
+constexpr int kAtPersistBlocksG32 = 98299;
 constexpr int kTripLd = kTripTile + 4;  // LDS row stride (floats)
 
 // DPP lane moves (all 64 lanes active): quad_perm xor 1 / xor 2 and
@@ -442,7 +446,8 @@ static void go_at(const MapGeom &g, const float *X, int64_t n, int64_t ldx, floa
                   double *eslots, unsigned long long *sslots, hipStream_t s) {
     const int r = at_group_lg(g.G, MAP, GRAD);
     const uint64_t groups = (g.G + (uint64_t(1) << r) - 1) >> r;
-    const uint64_t nblk = groups < uint64_t(kAtPersistBlocks) ? groups : uint64_t(kAtPersistBlocks);
+    const uint64_t cap = uint64_t(r == 5 ? kAtPersistBlocksG32 : kAtPersistBlocks);
+    const uint64_t nblk = groups < cap ? groups : cap;
     const dim3 grid(uint32_t(nblk > 0 ? nblk : 1));
     if (sslots)
         hipLaunchKernelGGL((at_kernel<MAP, GRAD, true>), grid, dim3(kTripThreads), 0, s, g, X, n, ldx, nu,
