@@ -30,13 +30,14 @@
 // triplet only adds three scalars.
 //
 // Block: 256 threads own the 32^3 triplets of tile (X, Y, Z), X <= Y <= Z, one
-// tile after another: the grid is persistent (at most kAtPersistBlocks blocks),
+// tile after another: the grid is persistent (at most kAtPersistBlocks blocks;
+// kAtPersistBlocksG32 when the groups below hold 32 ids),
 // the logical ids are dealt out in groups of R = 2^r consecutive ids (block b
 // taking groups b, b + grid, ...: every block samples the whole parallel space,
 // so blocks take equal time; R = 1 for the maps with many empty ids), and each
 // tile's positions are loaded while the previous tile's triplets run, so a
-// block no longer starts with a global load (the kernel took 64-65 ms with one
-// block per tile, 55 ms so).  Consecutive
+// block no longer starts with a global load (with one block per tile the
+// kernel took 64-65 ms, persistent 55 ms, before the changes below).  Consecutive
 // ids of every map here move one tile index and keep the other two (lambda3
 // walks w_x fastest: a Pi3 row changes X on one side of its fold and Z on the
 // other; the bounding box and the linear listing change X), so inside a group
@@ -69,9 +70,9 @@ namespace smx {
 
 constexpr int kTripThreads = 256;
 // persistent grid of the triplet kernels: about 32 blocks per resident block
-// slot (256 CUs x 3 blocks; measured flat from 16 to 128), and a prime, so that
-// a block's groups b, b + grid, ... do not keep to one position of the parallel
-// space's rows (which are powers of two or nb long).
+// slot (256 CUs x 3 blocks), and a prime, so that a block's ids or groups
+// b, b + grid, ... do not keep to one position of the parallel space's rows
+// (which are powers of two or nb long).
 constexpr int kAtPersistBlocks = 24571;
 // grid cap of the launches that deal groups of 32 (the largest ones: about one
 // group per block, 128 blocks per slot, also a prime): 53.3 -> 52.7 ms at
