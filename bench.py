@@ -78,7 +78,7 @@ def log(*a):
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+        print("bench.py runs on one GPU only: the library has no multi-GPU path "
               "(each step is one GPU's share at its real shape)", file=sys.stderr)
         sys.exit(2)
     import numpy as np

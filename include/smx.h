@@ -83,7 +83,7 @@ typedef enum {
     SMX_OK = 0,
     SMX_EINVAL = 1,      /* bad argument (null pointer, negative size, bad enum, ...) */
     SMX_EOVERFLOW = 2,   /* a size does not fit the index types */
-    SMX_EUNSUPPORTED = 3,/* valid request this build does not implement */
+    SMX_EUNSUPPORTED = 3,/* valid request the library does not implement */
     SMX_EHIP = 4         /* a HIP call or kernel launch failed */
 } smx_status;
 
