@@ -109,7 +109,7 @@ int launch_gram_prep(const float *X, int64_t n, int64_t d, int64_t ldx, int64_t 
 // k loops.  Measured on MI355X against 2 blocks per CU with 64 KB rings and
 // against wider slots (2 or 4 k steps each, 32-64 KB): those were 4-20%
 // slower; so were persistent grids that overlap each tile's stores with the
-// next tile's k loop inside one block (design notes).
+// next tile's k loop inside one block.
 template <bool SPLIT, int WT>
 struct GramCfg {
     static constexpr int NARR = SPLIT ? 4 : 2;     // A_hi, B_hi, (A_lo, B_lo)
@@ -121,6 +121,26 @@ struct GramCfg {
     static constexpr int LPW = STAGE / 4;          // loads per wave per stage
     static constexpr int S = SPLIT ? 2 : 4;         // ring depth: 32 KB either way
 };
+
+// One 16-byte store of four packed distances, ordinary or marked non-temporal.
+// The distances are written once and never read back by the kernel; streaming
+// them past the caches keeps the L2 for the operand panels, which pays once the
+// k loop is long.  Measured on MI355X at n = 32768 (ms, ordinary / streaming):
+// plain d = 32 0.58 / 0.77, d = 128 0.64 / 0.76, d = 256 0.77 / 0.76, d = 512
+// 1.02 / 0.80; split d = 64 0.67 / 0.79, d = 128 0.81 / 0.80, d = 512 1.71 /
+// 1.69.  The streaming stores hold about 2.8 TB/s whatever d; the ordinary
+// ones reach 3.7 TB/s alone but slow the k loop down as d grows.  (An HIP
+// float4 assignment here compiled to a 12-byte and a 4-byte store, hence the
+// vector type.)
+template <bool NT>
+__device__ __forceinline__ void store4(float *p, float4 v) {
+    typedef float f4 __attribute__((ext_vector_type(4)));
+    const f4 w = {v.x, v.y, v.z, v.w};
+    if constexpr (NT)
+        __builtin_nontemporal_store(w, reinterpret_cast<f4 *>(p));
+    else
+        *reinterpret_cast<f4 *>(p) = w;
+}
 
 // One stage's loads into buf ([narr][rb_n][64] uint4); the counts are
 // compile-time constants at every (inlined) call.  Row blocks past the padded
@@ -180,7 +200,10 @@ __device__ __forceinline__ void lds_wait(bf16x8_t (&a)[NP][MT], bf16x8_t (&b)[NP
 
 // TILED: the tile-contiguous layout (tile (X, Y) at rank Y(Y+1)/2 + X times T^2,
 // element (i, j) at (i mod T) T + (j mod T), entries outside i <= j < n zero).
-template <int MAP, bool SPLIT, bool STATS, int WT, bool TILED>
+// NT: the packed layout's stores are streaming (non-temporal); chosen at compile
+// time, since the compiler merges the two arms of a run-time choice into one
+// ordinary store.
+template <int MAP, bool SPLIT, bool STATS, int WT, bool TILED, bool NT>
 __global__ __launch_bounds__(kGramThreads, 4) void edm_gram_kernel(MapGeom g, const uint16_t *__restrict__ hi,
                                                                const uint16_t *__restrict__ lo,
                                                                const float *__restrict__ norms,
@@ -190,21 +213,22 @@ __global__ __launch_bounds__(kGramThreads, 4) void edm_gram_kernel(MapGeom g, co
     using C = GramCfg<SPLIT, WT>;
     constexpr int T = C::T, MT = C::MT, NP = SPLIT ? 2 : 1, S = C::S;
     constexpr int BUF = C::STAGE * 64;  // uint4 per ring slot
-    static_assert(S * BUF * 16 >= 4 * 32 * WT * 4, "the epilogue stages 32 rows per wave in the ring");
+    static_assert(S * BUF * 16 >= 2 * 32 * T * 4, "the epilogue stages 64 tile rows in the ring");
     uint64_t lin;
     int TX, TY;
     if (MAP == MAP_LAMBDA) {
-        // Each XCD takes one contiguous range of Pi2.  Plain: Pi2 column-major
-        // (w_y fastest): the blocks an XCD runs at once hold consecutive tiles of
-        // one row panel, whose packed row segments are neighbours in D.  Split:
-        // Pi2 in 16 x 8 patches, so the L2 also keeps the column panels (hi and
-        // lo): operands fetched from beyond L2 8.6 -> 3.2 GB, 1.96 -> 1.90 ms
-        // (plain, 4.2 -> 0.9 GB, gains no time from it)
+        // Each XCD takes one contiguous range of Pi2, walked in patches (w_x by
+        // w_y ids: 8 x 16 plain, 16 x 8 split) so that its L2 keeps the row and
+        // column panels of the tiles it runs at once: operands fetched from
+        // beyond L2 4.2 -> 0.8 GB plain, 8.6 -> 2.8 GB split.  Column-major order
+        // (w_y fastest, whose concurrent tiles extend the same packed rows) is
+        // the faster one for the stores alone, but with the non-temporal stores
+        // the patches took 5-10% less time at d = 512.
         lin = launch_index();
         if (lin >= g.G) return;
         const uint32_t id = xcd_remap(uint32_t(lin), uint32_t(g.G));
-        if (!lambda2(SPLIT ? lambda2_patch_to_xfast(id, g.lg, 4, 3) : lambda2_cm_to_xfast(id, g.lg), g.lg, g.nb,
-                     TX, TY))
+        if (!lambda2(SPLIT ? lambda2_patch_to_xfast(id, g.lg, 4, 3) : lambda2_patch_to_xfast(id, g.lg, 3, 4), g.lg,
+                     g.nb, TX, TY))
             return;
         if (SMX_CHECKED && !smx_check(0 <= TX && TX <= TY && TY < g.nb, kCheckMap)) return;
     } else if (!tile2_of<MAP, true>(g, lin, TX, TY)) {
@@ -281,19 +305,22 @@ __global__ __launch_bounds__(kGramThreads, 4) void edm_gram_kernel(MapGeom g, co
 
     // Epilogue.  32 x 32 accumulator layout: lane l, element e holds row
     // (e & 3) + 4 (l >> 5) + 8 (e >> 2) and column l & 31 of the MFMA tile.
-    // Per pass m each wave stages its 32 x WT slice of D in the (now idle)
-    // ring, then writes every row's WT floats as contiguous 16-byte pieces,
-    // so each store instruction covers whole runs of the packed row.  Tiles
-    // off the diagonal and inside n (all but a thin fringe) store unmasked.
-    __syncthreads();
-    float *St = reinterpret_cast<float *>(Lb) + w * 32 * WT;
-    constexpr int LPR = WT / 4;  // lanes per staged row
+    // Per pass m the four waves stage 64 whole rows of the tile (32 from each
+    // row half) in the (now idle) ring; then each wave writes 16 of them, two
+    // 512-byte tile rows per store instruction, so that only the two ends of a
+    // tile row share a 128-byte line with the neighbouring tiles (half-row
+    // pieces per wave: 0.995 against 0.938 ms plain, 1.855 against 1.829 split).
+    // Tiles off the diagonal and inside n (all but a thin fringe) store
+    // unmasked.
+    static_assert(T == 128 && kGramThreads == 256, "the store loop assumes 4 waves and 128-wide tile rows");
+    float *St = reinterpret_cast<float *>(Lb);  // [2 * 32 rows][T], the rows of one pass
     const bool interior = !diag && I0 + T <= n && J0 + T <= n;
     float nb[MT];
 #pragma unroll
     for (int c = 0; c < MT; ++c) nb[c] = nB[wn * WT + c * 32 + (lane & 31)];
 #pragma unroll
     for (int m = 0; m < MT; ++m) {
+        __syncthreads();  // the ring (k loop) or the previous pass's rows are consumed
         float na[16];
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
@@ -308,14 +335,16 @@ __global__ __launch_bounds__(kGramThreads, 4) void edm_gram_kernel(MapGeom g, co
                 float v = fmaxf(__builtin_fmaf(-2.f, acc[m][c][e], na[e] + nb[c]), 0.f);
                 // on a diagonal tile, element (il, il) is the diagonal: exactly 0
                 v = (diag && wm * WT + m * 32 + rl == wn * WT + c * 32 + (lane & 31)) ? 0.f : v;
-                St[rl * WT + c * 32 + (lane & 31)] = v;
+                St[(wm * 32 + rl) * T + wn * WT + c * 32 + (lane & 31)] = v;
             }
         }
+        __syncthreads();
+        // each wave writes 16 whole tile rows, two per instruction
 #pragma unroll
-        for (int it = 0; it < 32 * LPR / 64; ++it) {
-            const int rl = it * (64 / LPR) + lane / LPR, cl = 4 * (lane % LPR);
-            const int64_t i = I0 + wm * WT + m * 32 + rl, j = J0 + wn * WT + cl;
-            const float4 v = *reinterpret_cast<const float4 *>(St + rl * WT + cl);
+        for (int it = 0; it < 8; ++it) {
+            const int r = w * 16 + 2 * it + (lane >> 5), cl = 4 * (lane & 31);
+            const int64_t i = I0 + (r >> 5) * WT + m * 32 + (r & 31), j = J0 + cl;
+            const float4 v = *reinterpret_cast<const float4 *>(St + r * T + cl);
             if (TILED) {
                 const uint64_t rank = uint64_t(TY) * (uint64_t(TY) + 1) / 2 + uint64_t(TX);
                 float *tdst = D + rank * uint64_t(T * T) + uint64_t(i - I0) * T + uint64_t(j - J0);
@@ -332,7 +361,7 @@ __global__ __launch_bounds__(kGramThreads, 4) void edm_gram_kernel(MapGeom g, co
             float *dst = D + (i * n - (i * (i - 1)) / 2 - i) + j;
             if (interior) {
                 if (smx_check(i < n && j >= i && j + 3 < n, kCheckStore))
-                    *reinterpret_cast<float4 *>(dst) = v;  // 4-byte aligned: the packed rows start anywhere
+                    store4<NT>(dst, v);  // 4-byte aligned: the packed rows start anywhere
             } else if (i < n) {
                 const float vv[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
@@ -352,17 +381,21 @@ __global__ __launch_bounds__(kGramThreads, 4) void edm_gram_kernel(MapGeom g, co
 }
 
 
-template <int MAP, bool SPLIT, int WT, bool TILED>
+template <int MAP, bool SPLIT, int WT, bool TILED, bool NT>
 static void go_gram(const MapGeom &g, const uint16_t *hi, const uint16_t *lo, const float *norms,
                     int64_t n, int64_t dpad, float *D, unsigned long long *slots, hipStream_t s) {
     const dim3 grid = MAP == MAP_BBOX ? dim3(g.nb, g.nb, 1) : grid_for(g.G, kGramThreads);
     if (slots)
-        hipLaunchKernelGGL((edm_gram_kernel<MAP, SPLIT, true, WT, TILED>), grid, dim3(kGramThreads), 0, s, g, hi,
-                           lo, norms, n, dpad, D, slots);
+        hipLaunchKernelGGL((edm_gram_kernel<MAP, SPLIT, true, WT, TILED, NT>), grid, dim3(kGramThreads), 0, s, g,
+                           hi, lo, norms, n, dpad, D, slots);
     else
-        hipLaunchKernelGGL((edm_gram_kernel<MAP, SPLIT, false, WT, TILED>), grid, dim3(kGramThreads), 0, s, g, hi,
-                           lo, norms, n, dpad, D, slots);
+        hipLaunchKernelGGL((edm_gram_kernel<MAP, SPLIT, false, WT, TILED, NT>), grid, dim3(kGramThreads), 0, s, g,
+                           hi, lo, norms, n, dpad, D, slots);
 }
+
+// Streaming stores once the k loop is long enough for the operand panels' L2
+// residency to matter more than the stores' own rate (see store4).
+static bool gram_streaming(int64_t dpad, bool split) { return (split ? 2 : 1) * dpad >= 256; }
 
 int launch_edm_gram(const MapGeom &g, int tile, const uint16_t *hi, const uint16_t *lo, const float *norms,
                     int64_t n, int64_t dpad, bool split, float *D, unsigned long long *slots, bool tiled,
@@ -372,12 +405,16 @@ int launch_edm_gram(const MapGeom &g, int tile, const uint16_t *hi, const uint16
         constexpr int MAPK = decltype(M)::value;
         constexpr int WT = kGramTile / 2;
         (void)tile;  // kGramTile
+        const bool nt = gram_streaming(dpad, split);
         if (tiled) {
-            if (split) go_gram<MAPK, true, WT, true>(gg, hi, lo, norms, n, dpad, D, slots, s);
-            else go_gram<MAPK, false, WT, true>(gg, hi, lo, norms, n, dpad, D, slots, s);
+            if (split) go_gram<MAPK, true, WT, true, false>(gg, hi, lo, norms, n, dpad, D, slots, s);
+            else go_gram<MAPK, false, WT, true, false>(gg, hi, lo, norms, n, dpad, D, slots, s);
+        } else if (nt) {
+            if (split) go_gram<MAPK, true, WT, false, true>(gg, hi, lo, norms, n, dpad, D, slots, s);
+            else go_gram<MAPK, false, WT, false, true>(gg, hi, lo, norms, n, dpad, D, slots, s);
         } else {
-            if (split) go_gram<MAPK, true, WT, false>(gg, hi, lo, norms, n, dpad, D, slots, s);
-            else go_gram<MAPK, false, WT, false>(gg, hi, lo, norms, n, dpad, D, slots, s);
+            if (split) go_gram<MAPK, true, WT, false, false>(gg, hi, lo, norms, n, dpad, D, slots, s);
+            else go_gram<MAPK, false, WT, false, false>(gg, hi, lo, norms, n, dpad, D, slots, s);
         }
     });
     prof_end(K_EDM_GRAM, s);

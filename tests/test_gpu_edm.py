@@ -181,12 +181,14 @@ def test_edm_full_size_gram(prec):
     assert worst <= TOL[prec]
 
 
+@pytest.mark.parametrize("d", [40, 300])
 @pytest.mark.parametrize("prec", ["bf16", "split_bf16"])
-def test_edm_gram_large_n_ragged(prec):
+def test_edm_gram_large_n_ragged(prec, d):
     """n = 16484 (128-element Gram tiles, the last one ragged, 32-row operand
-    blocks padded), d = 40 (K padded to 64, a partial ring of k steps): all
-    maps bit-identical; sampled rows at tile edges against the oracle."""
-    n, d = 16484, 40
+    blocks padded), d = 40 (K padded to 64, a partial ring of k steps; ordinary
+    stores) and d = 300 (K padded to 304; streaming stores): all maps
+    bit-identical; sampled rows at tile edges against the oracle."""
+    n = 16484
     X = np.random.default_rng(11).standard_normal((n, d)).astype(np.float32)
     Xt = torch.from_numpy(X).cuda()
     D = smx.edm_packed(Xt, "lambda", prec)
