@@ -129,9 +129,10 @@ struct GramCfg {
 // plain d = 32 0.58 / 0.77, d = 128 0.64 / 0.76, d = 256 0.77 / 0.76, d = 512
 // 1.02 / 0.80; split d = 64 0.67 / 0.79, d = 128 0.81 / 0.80, d = 512 1.71 /
 // 1.69.  The streaming stores hold about 2.8 TB/s whatever d; the ordinary
-// ones reach 3.7 TB/s alone but slow the k loop down as d grows.  (An HIP
-// float4 assignment here compiled to a 12-byte and a 4-byte store, hence the
-// vector type.)
+// ones reach 3.7 TB/s alone but slow the k loop down as d grows.  The
+// tile-contiguous layout (aligned 64 KB runs) follows the same rule: plain
+// d = 32 0.37 / 0.37, d = 512 0.83 / 0.74.  (An HIP float4 assignment here
+// compiled to a 12-byte and a 4-byte store, hence the vector type.)
 template <bool NT>
 __device__ __forceinline__ void store4(float *p, float4 v) {
     typedef float f4 __attribute__((ext_vector_type(4)));
@@ -200,9 +201,9 @@ __device__ __forceinline__ void lds_wait(bf16x8_t (&a)[NP][MT], bf16x8_t (&b)[NP
 
 // TILED: the tile-contiguous layout (tile (X, Y) at rank Y(Y+1)/2 + X times T^2,
 // element (i, j) at (i mod T) T + (j mod T), entries outside i <= j < n zero).
-// NT: the packed layout's stores are streaming (non-temporal); chosen at compile
-// time, since the compiler merges the two arms of a run-time choice into one
-// ordinary store.
+// NT: the output stores are streaming (non-temporal); chosen at compile time,
+// since the compiler merges the two arms of a run-time choice into one ordinary
+// store.
 template <int MAP, bool SPLIT, bool STATS, int WT, bool TILED, bool NT>
 __global__ __launch_bounds__(kGramThreads, 4) void edm_gram_kernel(MapGeom g, const uint16_t *__restrict__ hi,
                                                                const uint16_t *__restrict__ lo,
@@ -355,7 +356,7 @@ __global__ __launch_bounds__(kGramThreads, 4) void edm_gram_kernel(MapGeom g, co
                     o.z = (i < n && j + 2 < n && j + 2 >= i) ? v.z : 0.f;
                     o.w = (i < n && j + 3 < n && j + 3 >= i) ? v.w : 0.f;
                 }
-                *reinterpret_cast<float4 *>(tdst) = o;  // 16-byte aligned: tiles start at multiples of T^2
+                store4<NT>(tdst, o);  // 16-byte aligned: tiles start at multiples of T^2
                 continue;
             }
             float *dst = D + (i * n - (i * (i - 1)) / 2 - i) + j;
@@ -406,7 +407,10 @@ int launch_edm_gram(const MapGeom &g, int tile, const uint16_t *hi, const uint16
         constexpr int WT = kGramTile / 2;
         (void)tile;  // kGramTile
         const bool nt = gram_streaming(dpad, split);
-        if (tiled) {
+        if (tiled && nt) {
+            if (split) go_gram<MAPK, true, WT, true, true>(gg, hi, lo, norms, n, dpad, D, slots, s);
+            else go_gram<MAPK, false, WT, true, true>(gg, hi, lo, norms, n, dpad, D, slots, s);
+        } else if (tiled) {
             if (split) go_gram<MAPK, true, WT, true, false>(gg, hi, lo, norms, n, dpad, D, slots, s);
             else go_gram<MAPK, false, WT, true, false>(gg, hi, lo, norms, n, dpad, D, slots, s);
         } else if (nt) {
