@@ -234,6 +234,32 @@ def test_edm_tiled_layout_matches_packed(n, d, prec):
         assert (T[rest] == 0).all()
 
 
+@pytest.mark.parametrize("d", [112, 128, 240, 256])
+@pytest.mark.parametrize("prec", ["bf16", "split_bf16"])
+def test_edm_gram_store_kinds(d, prec):
+    """The Gram kernel writes with ordinary or streaming (non-temporal) stores
+    by the padded depth (plain BF16 streams from d_pad = 256, split from 128),
+    so these d sit on both sides of both switches.  At n = 300 tile (0, 1) is
+    interior (unmasked stores) and the rest is fringe.  Element by element
+    against the oracle, every map bit-identical, and the tile-contiguous layout
+    holding the same values."""
+    n = 300
+    X = synth.normal(n, d, seed=500 + d)
+    ref = oracle.edm_packed(X)
+    outs = [_edm(X, k, prec).cpu().numpy() for k in KINDS]
+    for o in outs[1:]:
+        np.testing.assert_array_equal(o, outs[0])
+    D = outs[0].astype(np.float64)
+    assert (D >= 0).all()
+    err = _errors(D, ref, X, prec)
+    print(f"  max error {err:.3e}")
+    assert err <= TOL[prec]
+    ii = np.concatenate([np.full(n - i, i) for i in range(n)])
+    jj = np.concatenate([np.arange(i, n) for i in range(n)])
+    T = smx.edm_tiled(torch.from_numpy(X).cuda(), "lambda", prec).cpu().numpy()
+    np.testing.assert_array_equal(T[_tiled_edm_offsets(ii, jj)], outs[0])
+
+
 @pytest.mark.parametrize("prec", ["fp32", "split_bf16"])
 def test_edm_tiled_full_size_rows(prec):
     """Full-size inputs (n = 65536, d = 64 FP32; n = 32768, d = 512 split BF16):
