@@ -131,7 +131,7 @@ struct GramCfg {
 // 1.69.  The streaming stores hold about 2.8 TB/s whatever d; the ordinary
 // ones reach 3.7 TB/s alone but slow the k loop down as d grows.  The
 // tile-contiguous layout (aligned 64 KB runs) follows the same rule: plain
-// d = 32 0.37 / 0.37, d = 512 0.83 / 0.74.  (An HIP float4 assignment here
+// d = 32 0.37 / 0.37, d = 512 0.83 / 0.74.  (A HIP float4 assignment here
 // compiled to a 12-byte and a 4-byte store, hence the vector type.)
 template <bool NT>
 __device__ __forceinline__ void store4(float *p, float4 v) {
